@@ -1,0 +1,233 @@
+/*
+ * depo.h - C ABI of the MI355X (gfx950) Lagrangian particle-deposition step.
+ *
+ * The library advances the particles of the high-fidelity model of
+ * Yao, Huan & Capecelatro, "Multi-fidelity uncertainty quantification of
+ * particle deposition in turbulent pipe flow" (arXiv 2205.04979) through a
+ * frozen carrier-gas velocity field: fluid velocity at the particle
+ * (Appendix A.2.1), Schiller-Naumann drag (Eq. part_source), pairwise
+ * Coulomb forces (Eq. coulomb, Appendix A.2.4), soft-sphere contact
+ * (Appendix A.2.2) with van der Waals cohesion (Eq. vdw, Appendix A.2.3),
+ * wall image charge and wall cohesion (Section 2.2, Appendix B.2), time
+ * integration of Newton's law (Eq. newtonlaw), removal of particles that
+ * touch the wall (Appendix A) and the deposition tally that gives V_dep
+ * (Eq. 2).  Several independent Monte Carlo samples with their own charge
+ * scale, Hamaker constant and temperature (Sections 2.1, 3, 4.4) can share
+ * one field and one launch.
+ *
+ * Conventions
+ * -----------
+ * - Units are SI; every host-side floating-point input is double.
+ * - Memory: the library allocates no device memory.  The caller allocates
+ *   one device workspace of depo_workspace_bytes() bytes (for instance a
+ *   torch uint8 tensor) and hands it to depo_bind(); the workspace must stay
+ *   alive and unmoved until depo_destroy() or the next depo_bind().  Host
+ *   arrays are borrowed for the duration of the call only.
+ * - Streams: every entry point that takes a depo_stream enqueues its device
+ *   work on that HIP stream (NULL = the legacy default stream).  Calls that
+ *   return data to the host synchronise that stream before returning.
+ * - Errors: every entry point returns a depo_status.  Arguments are validated
+ *   on the host before anything is enqueued; on an error nothing is enqueued
+ *   and depo_last_error() describes the problem.  Device-side conditions
+ *   (a non-finite velocity or acceleration) are recorded in a sticky flag and
+ *   reported by the next call that synchronises (depo_tally_read,
+ *   depo_read_particles, depo_state_download).  After DEPO_E_HIP the context
+ *   should be destroyed.
+ * - Threading: a context is used by one host thread at a time.
+ * - Precision: params.real_bytes = 4 selects the FP32 form (positions stored
+ *   as 32-bit fixed point, velocities/forces FP32, compensated summation of
+ *   the Coulomb sums, FP64 wall test and tally); 8 selects FP64 throughout
+ *   (positions as 64-bit fixed point).
+ * - Layout of particle arrays on the host: [N][3] row-major for vectors,
+ *   [N] for scalars; particles of sample s occupy rows
+ *   offsets[s] .. offsets[s+1]-1.
+ */
+#ifndef DEPO_H
+#define DEPO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct depo_ctx depo_ctx;   /* opaque, library-owned host object */
+typedef void *depo_stream;          /* a hipStream_t; NULL = default stream */
+
+typedef enum {
+  DEPO_OK = 0,
+  DEPO_E_INVALID = -1,    /* bad argument; nothing was enqueued                 */
+  DEPO_E_STATE = -2,      /* call out of order (e.g. step before seed)          */
+  DEPO_E_HIP = -3,        /* HIP runtime error; destroy the context            */
+  DEPO_E_NONFINITE = -4,  /* a velocity or acceleration became NaN/Inf         */
+  DEPO_E_CAPACITY = -5,   /* workspace too small for the requested layout      */
+  DEPO_E_CORRUPT = -6     /* checkpoint blob failed its size/format/CRC checks */
+} depo_status;
+
+/* Force and behaviour switches (depo_params.flags). */
+enum {
+  DEPO_DRAG = 1u << 0,        /* Schiller-Naumann drag, Eq. part_source                       */
+  DEPO_COULOMB = 1u << 1,     /* pairwise Coulomb force, Eq. coulomb (direct O(N^2) sum)      */
+  DEPO_COLLIDE = 1u << 2,     /* soft-sphere normal contact, Appendix A.2.2                   */
+  DEPO_VDW = 1u << 3,         /* pair van der Waals cohesion, Eq. vdw                         */
+  DEPO_VDW_GU = 1u << 4,      /* soft-sphere saturation gap delta_min (k_r/k)^(1/4), A.2.3    */
+  DEPO_WALL_IMAGE = 1u << 5,  /* image-charge attraction to the wall, Section 2.2 / App. B.2  */
+  DEPO_WALL_VDW = 1u << 6,    /* sphere-plane cohesion with the wall, Section 2.2 / App. B.2  */
+  DEPO_REBOUND_OSU = 1u << 7, /* temperature-dependent stick/rebound at the wall, Eq. CoR     */
+  DEPO_SOFT_TALLY = 1u << 8,  /* no removal; smoothed deposition tally (differentiable)       */
+  DEPO_BODY_FORCE = 1u << 9   /* constant body acceleration g_body (used by tests)            */
+};
+
+/* Physical and numerical parameters, SI.  Validated by depo_create(). */
+typedef struct {
+  double R;            /* pipe radius [m] (> 0)                                         */
+  double L;            /* periodic pipe length [m] (>= 2R)                              */
+  double nu;           /* kinematic viscosity of the gas [m^2/s]                        */
+  double rho_f;        /* gas density [kg/m^3]                                          */
+  double rho_p;        /* particle material density [kg/m^3]                            */
+  double dt;           /* time step [s]                                                 */
+  double re_tau;       /* friction Reynolds number u* R / nu (only scales V_dep+)       */
+  double e_pp;         /* particle-particle restitution coefficient, 0 < e <= 1          */
+  int32_t tau_col_steps; /* contact duration in time steps (paper: 15)                  */
+  int32_t real_bytes;  /* 4 = FP32 form, 8 = FP64                                       */
+  double delta_min;    /* van der Waals saturation gap [m] (paper: 1e-9)                */
+  double kr_over_k;    /* real / simulated contact stiffness (paper: 700)               */
+  double eps0;         /* vacuum permittivity [F/m]                                     */
+  double g_body[3];    /* body acceleration [m/s^2], used with DEPO_BODY_FORCE          */
+  double E_young;      /* particle Young's modulus [Pa] (rebound law)                   */
+  double delta_c;      /* cohesion length of the rebound law [m]                        */
+  double acont_coef;   /* wall contact area = acont_coef * pi d^2 / 4                   */
+  double soft_eps;     /* smoothed tally width, fraction of d                           */
+  double soft_tau;     /* smoothed tally time scale, in time steps                      */
+  uint32_t flags;      /* DEPO_* switches                                               */
+  uint32_t reserved;   /* must be 0                                                     */
+} depo_params;
+
+/* Per-sample inputs of the uncertainty study (Sections 2.1 and 4.4):
+ * particle charge q_i = charge_scale * qbase_i, Hamaker constant A [J],
+ * particle temperature T [K] (enters only the rebound law). */
+typedef struct {
+  double charge_scale;
+  double hamaker;
+  double temperature;
+} depo_sample_params;
+
+/* Per-sample deposition tally (Eq. 2). */
+typedef struct {
+  double m_dep;       /* deposited mass [kg]                                           */
+  int64_t n_dep;      /* deposited particle count                                      */
+  double m_alive_dt;  /* time integral of the suspended mass [kg s]                    */
+  double t;           /* simulated time [s]                                            */
+  double v_dep;       /* deposition velocity (R/2) m_dep / m_alive_dt [m/s]            */
+  double v_dep_plus;  /* V_dep / u*                                                    */
+  double v_dep_se;    /* Poisson standard error of v_dep                               */
+  double j_soft;      /* smoothed deposited mass sum_i m_i (1 - exp(-l_i)) [kg]        */
+  int64_t n_alive;    /* particles still suspended                                     */
+} depo_tally;
+
+/* Human-readable name of a status code.  Never NULL; static storage. */
+const char *depo_status_string(int status);
+
+/* Create a context from validated parameters.  Host only, touches no GPU.
+ * Returns DEPO_E_INVALID (with *out = NULL) for non-positive or non-finite
+ * lengths, densities, viscosity or dt, e_pp outside (0, 1], tau_col_steps < 1,
+ * real_bytes not 4 or 8, L < 2R, unknown flag bits or reserved != 0. */
+depo_status depo_create(const depo_params *p, depo_ctx **out);
+
+/* Destroy a context and its host-side objects (graphs, staging).  Never frees
+ * the caller's workspace.  NULL is ignored. */
+void depo_destroy(depo_ctx *ctx);
+
+/* Message of the last failed call on ctx ("" if none); valid until the next call. */
+const char *depo_last_error(const depo_ctx *ctx);
+
+/* Declare the batch layout: n_samples >= 1 samples, offsets[n_samples+1]
+ * non-decreasing from 0 with N = offsets[n_samples] <= 2^26 particles, and the
+ * field grid nx, ny, nz (each 4..4096; nodes x_i = i L / nx periodic,
+ * y_j = -R + 2R j/(ny-1), z_k = -R + 2R k/(nz-1)).  Host only.  Resets the
+ * binding and the seeded state. */
+depo_status depo_set_layout(depo_ctx *ctx, int32_t n_samples, const int64_t *offsets,
+                            int32_t nx, int32_t ny, int32_t nz);
+
+/* Device workspace size for the current layout.  Host only. */
+depo_status depo_workspace_bytes(const depo_ctx *ctx, size_t *bytes);
+
+/* Bind a caller-owned device workspace (256-byte aligned, at least
+ * depo_workspace_bytes() bytes; DEPO_E_CAPACITY otherwise).  Clears the
+ * library's counters on the default stream and waits for it. */
+depo_status depo_bind(depo_ctx *ctx, void *d_work, size_t bytes);
+
+/* Upload the carrier-gas velocity on the node grid declared by
+ * depo_set_layout: h_uvw[nx][ny][nz][3] (z fastest), copied and converted
+ * to the working precision.  Synchronises the stream. */
+depo_status depo_init_field(depo_ctx *ctx, const double *h_uvw, depo_stream stream);
+
+/* Seed the particles: per-sample parameters sp[n_samples]; positions
+ * h_x3[N][3] with 0 <= x < L (x is wrapped) and y^2 + z^2 < R^2; diameters
+ * h_d[N] in (0, R/4); base charges h_qbase[N].  h_v3[N][3] may be NULL, in
+ * which case each particle starts at the local fluid velocity.  Computes the
+ * initial acceleration (all forces at the seeded positions) and resets the
+ * tally and the step counter.  Synchronises the stream. */
+depo_status depo_seed(depo_ctx *ctx, const depo_sample_params *sp, const double *h_x3,
+                      const double *h_v3, const double *h_d, const double *h_qbase,
+                      depo_stream stream);
+
+/* Replace the per-sample parameters without touching the particle state
+ * (charges are rebuilt from the stored base charges).  Synchronises the stream. */
+depo_status depo_set_sample_params(depo_ctx *ctx, const depo_sample_params *sp, depo_stream stream);
+
+/* Advance all samples by n_steps >= 0 time steps.  Asynchronous: enqueues
+ * the step sequence n_steps times on the stream (replaying a captured HIP
+ * graph when possible) and returns without waiting. */
+depo_status depo_step(depo_ctx *ctx, int32_t n_steps, depo_stream stream);
+
+/* Same as depo_step without graph replay, with HIP events recorded on the
+ * stream between the kernel families of every step; h_phase_ms[5] receives
+ * the summed durations of (particle update before the forces, cell-list build,
+ * Coulomb pair sums, short-range forces, force assembly and second half kick)
+ * in milliseconds.  1 <= n_steps <= 100000.  Synchronises the stream. */
+depo_status depo_step_timed(depo_ctx *ctx, int32_t n_steps, depo_stream stream, double *h_phase_ms);
+
+/* Choose the Coulomb pair-kernel shape (targets per lane, wavefronts per
+ * workgroup, sources per compensated block) and whether depo_step replays a
+ * captured HIP graph (use_graph != 0, the default) or launches kernels
+ * directly.  DEPO_E_INVALID for a shape that is not compiled in.  Defaults:
+ * (1, 8, 32) in FP32, (1, 4, 16) in FP64. */
+depo_status depo_set_kernel_config(depo_ctx *ctx, int32_t targets_per_lane, int32_t waves, int32_t block,
+                                   int32_t use_graph);
+
+/* Recompute the non-drag acceleration of every alive particle at the
+ * current positions and velocities (the force evaluation of a step without
+ * moving anything), and the fluid velocity at each particle.  Async. */
+depo_status depo_eval_accel(depo_ctx *ctx, depo_stream stream);
+
+/* Copy the particle state to the host, converted to SI doubles: positions
+ * [N][3] (x in [0, L)), velocities [N][3], non-drag accelerations [N][3],
+ * the step at which each particle deposited (0 = suspended) and the number
+ * of short-range neighbours of each particle found at the last force
+ * evaluation.  Any pointer may be NULL.  Synchronises the stream. */
+depo_status depo_read_particles(depo_ctx *ctx, double *h_x3, double *h_v3, double *h_a3,
+                                int32_t *h_dep_step, int32_t *h_neighbours, depo_stream stream);
+
+/* Per-sample tallies out[n_samples] (Eq. 2).  Reduces on the device in a
+ * fixed order (bitwise reproducible) and synchronises the stream. */
+depo_status depo_tally_read(depo_ctx *ctx, depo_tally *out, depo_stream stream);
+
+/* Checkpoint blob size for the current layout and precision.  Host only. */
+depo_status depo_state_bytes(const depo_ctx *ctx, size_t *bytes);
+
+/* Write the full particle state and step counter into h_blob (exactly
+ * depo_state_bytes() bytes, with a CRC32).  Synchronises the stream. */
+depo_status depo_state_download(depo_ctx *ctx, void *h_blob, size_t bytes, depo_stream stream);
+
+/* Restore a blob written by depo_state_download for the same layout and
+ * precision; DEPO_E_CORRUPT on a size, format or CRC mismatch (nothing is
+ * changed then).  Synchronises the stream. */
+depo_status depo_state_upload(depo_ctx *ctx, const void *h_blob, size_t bytes, depo_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEPO_H */

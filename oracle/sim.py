@@ -41,7 +41,9 @@ from .gather import trilinear
 class OracleSim:
     """Plain float64 simulation of one or more Monte Carlo samples sharing one field."""
 
-    def __init__(self, params: dict, field: np.ndarray, x0, d, qbase, offsets, sample_params, v0=None):
+    def __init__(self, params: dict, field: np.ndarray, x0, d, qbase, offsets, sample_params, v0=None,
+                 evaluate: bool = True):
+        """Seed the particles; with ``evaluate`` the initial acceleration a^0 is computed (all pairs)."""
         p = dict(params)
         self.p = p
         self.field = np.asarray(field, dtype=np.float64)
@@ -69,7 +71,7 @@ class OracleSim:
         self.m_alive_dt = np.zeros(S)
         self.uf = trilinear(self.field, self.R, self.L, self.x)
         self.v = self.uf.copy() if v0 is None else np.array(v0, dtype=np.float64).reshape(N, 3)
-        self.a = self.accelerations()
+        self.a = self.accelerations() if evaluate else np.zeros((N, 3))
 
     # ------------------------------------------------------------------ per-sample parameters
     @property

@@ -1,0 +1,835 @@
+// C ABI of the deposition step (include/depo.h): validation, workspace
+// planning, uploads, the per-step launch sequence (optionally replayed from a
+// captured HIP graph), tallies and checkpoints.  Host code only; the kernels
+// live in k_particle.hip, k_coulomb.hip and k_cells.hip.
+#include "depo.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+using namespace depo;
+
+namespace {
+
+constexpr uint32_t kKnownFlags = (1u << 10) - 1;
+constexpr int kMaxN = 1 << 26;
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+uint32_t crc32_update(uint32_t crc, const void *data, size_t n) {
+  static uint32_t table[256];
+  static bool init = false;
+  if (!init) {
+    for (uint32_t i = 0; i < 256; ++i) {
+      uint32_t c = i;
+      for (int k = 0; k < 8; ++k) c = (c & 1) ? 0xEDB88320u ^ (c >> 1) : c >> 1;
+      table[i] = c;
+    }
+    init = true;
+  }
+  const uint8_t *p = (const uint8_t *)data;
+  crc = ~crc;
+  for (size_t i = 0; i < n; ++i) crc = table[(crc ^ p[i]) & 0xFF] ^ (crc >> 8);
+  return ~crc;
+}
+
+struct BlobHeader {
+  char magic[8];
+  uint32_t version, real_bytes;
+  int64_t n;
+  int32_t s, nstep;
+  uint64_t payload;
+  uint32_t crc, pad;
+};
+
+}  // namespace
+
+struct depo_ctx {
+  depo_params p{};
+  std::string err;
+  // layout
+  bool has_layout = false;
+  int S = 0;
+  int64_t N = 0;
+  std::vector<int64_t> off;
+  int nx = 0, ny = 0, nz = 0;
+  int64_t cell_cap = 0;
+  int scan_blocks = 0;
+  int tile_cap = 0;
+  // workspace
+  size_t ws_need = 0;
+  char *ws = nullptr;
+  bool bound = false, field_ready = false, seeded = false;
+  // state
+  int nstep = 0;
+  int n_cells = 0;
+  int n_tiles = 0;
+  std::vector<SampleDev> samples;
+  std::vector<depo_sample_params> sp;
+  CoulombConfig ccfg{1, 8, 32};
+  Phys ph{};
+  State<float> sf{};
+  State<double> sd{};
+  // captured step graph
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  bool use_graph = true;
+
+  bool fp64() const { return p.real_bytes == 8; }
+  depo_status fail(depo_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    return st;
+  }
+  void drop_graph() {
+    if (gexec) hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+  }
+};
+
+#define HIP_TRY(call)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return ctx->fail(DEPO_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Carve the workspace (base == nullptr: only size it).
+template <class Real>
+size_t carve(depo_ctx *ctx, char *base, State<Real> &st) {
+  using Pos = typename Prec<Real>::Pos;
+  const size_t N = (size_t)std::max<int64_t>(ctx->N, 1);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    char *p = base ? base + o : nullptr;
+    o = align_up(o + bytes);
+    return p;
+  };
+  st.px = (Pos *)take(N * sizeof(Pos));
+  st.py = (Pos *)take(N * sizeof(Pos));
+  st.pz = (Pos *)take(N * sizeof(Pos));
+  Real **reals[] = {&st.vx, &st.vy, &st.vz, &st.ax, &st.ay, &st.az, &st.ux, &st.uy,
+                    &st.uz, &st.cx, &st.cy, &st.cz, &st.sx, &st.sy, &st.sz, &st.jr};
+  for (Real **r : reals) *r = (Real *)take(N * sizeof(Real));
+  st.d = (double *)take(N * sizeof(double));
+  st.qb = (double *)take(N * sizeof(double));
+  st.ell = (double *)take(N * sizeof(double));
+  st.dep = (int32_t *)take(N * 4);
+  st.sid = (int32_t *)take(N * 4);
+  st.nbr = (int32_t *)take(N * 4);
+  st.cell_of = (int32_t *)take(N * 4);
+  st.cell_idx = (int32_t *)take(N * 4);
+  st.cell_count = (int32_t *)take((size_t)ctx->cell_cap * 4);
+  st.cell_start = (int32_t *)take(((size_t)ctx->cell_cap + 1) * 4);
+  st.scan_part = (int32_t *)take((size_t)std::max(ctx->scan_blocks, 1) * 4);
+  st.js = (JSrc<Real> *)take(N * sizeof(JSrc<Real>));
+  st.samples = (SampleDev *)take((size_t)ctx->S * sizeof(SampleDev));
+  st.tiles = (TileDev *)take((size_t)std::max(ctx->tile_cap, 1) * sizeof(TileDev));
+  st.field = (typename Prec<Real>::Vec4 *)take((size_t)ctx->nx * ctx->ny * ctx->nz * sizeof(typename Prec<Real>::Vec4));
+  st.nstep = (int32_t *)take(64);
+  st.err = (uint32_t *)take(64);
+  st.tally = (double *)take((size_t)ctx->S * 8 * sizeof(double));
+  return o;
+}
+
+template <class Real> State<Real> &state(depo_ctx *ctx);
+template <> State<float> &state<float>(depo_ctx *ctx) { return ctx->sf; }
+template <> State<double> &state<double>(depo_ctx *ctx) { return ctx->sd; }
+
+void fill_phys(depo_ctx *ctx) {
+  const depo_params &p = ctx->p;
+  Phys &ph = ctx->ph;
+  const int B = ctx->fp64() ? 64 : 32;
+  ph.flags = p.flags;
+  ph.R = p.R;
+  ph.L = p.L;
+  ph.ux = p.L * std::ldexp(1.0, -B);
+  ph.ur = p.R * std::ldexp(1.0, -(B - 2));
+  ph.inv_ux = 1.0 / ph.ux;
+  ph.inv_ur = 1.0 / ph.ur;
+  ph.dt = p.dt;
+  ph.nu = p.nu;
+  ph.rho_p = p.rho_p;
+  ph.rho_f = p.rho_f;
+  ph.tau_coef = p.rho_p / (18.0 * p.rho_f * p.nu);
+  ph.mass_coef = p.rho_p * M_PI / 6.0;
+  ph.k_e = 1.0 / (4.0 * M_PI * p.eps0);
+  ph.q_ref = 1e-15;
+  ph.yz_over_x = ph.ur / ph.ux;
+  ph.delta_sat = (p.flags & DEPO_VDW_GU) ? p.delta_min * std::pow(p.kr_over_k, 0.25) : p.delta_min;
+  const double tau_col = p.tau_col_steps * p.dt;
+  const double le = std::log(p.e_pp);
+  ph.col_K = (M_PI * M_PI + le * le) / (tau_col * tau_col);
+  ph.col_H = -2.0 * le / tau_col;
+  for (int k = 0; k < 3; ++k) ph.g_body[k] = p.g_body[k];
+  ph.E_young = p.E_young;
+  ph.delta_c = p.delta_c;
+  ph.acont_coef = p.acont_coef;
+  ph.soft_eps = p.soft_eps;
+  ph.soft_rate = (p.soft_tau > 0.0) ? 1.0 / (p.soft_tau * p.dt) : 0.0;
+  ph.N = (int32_t)ctx->N;
+  ph.S = ctx->S;
+  ph.nx = ctx->nx;
+  ph.ny = ctx->ny;
+  ph.nz = ctx->nz;
+}
+
+void build_tiles(depo_ctx *ctx, std::vector<TileDev> &tiles) {
+  const int T = coulomb_tile_targets(ctx->ccfg);
+  std::vector<int> order(ctx->S);
+  for (int s = 0; s < ctx->S; ++s) order[s] = s;
+  // longest samples first: their tiles cost the most (work ~ N_s per tile)
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return ctx->off[a + 1] - ctx->off[a] > ctx->off[b + 1] - ctx->off[b];
+  });
+  tiles.clear();
+  for (int s : order) {
+    const int64_t b = ctx->off[s], e = ctx->off[s + 1];
+    for (int64_t i = b; i < e; i += T)
+      tiles.push_back(TileDev{(int32_t)i, (int32_t)std::min<int64_t>(T, e - i), (int32_t)b, (int32_t)(e - b)});
+  }
+}
+
+bool short_range_on(const depo_ctx *ctx) { return (ctx->p.flags & (DEPO_COLLIDE | DEPO_VDW)) != 0; }
+
+// Enqueue the force evaluation at the current positions (prepare has run).
+template <class Real> void enqueue_forces(depo_ctx *ctx, hipStream_t s) {
+  const State<Real> &st = state<Real>(ctx);
+  if (short_range_on(ctx)) launch_cells<Real>(st, ctx->ph, ctx->n_cells, (ctx->n_cells + 1023) / 1024, s);
+  if (ctx->p.flags & DEPO_COULOMB) launch_coulomb<Real>(st, ctx->ph, ctx->n_tiles, ctx->ccfg, s);
+  if (short_range_on(ctx)) launch_short_range<Real>(st, ctx->ph, s);
+}
+
+int prepare_mode(const depo_ctx *ctx) {
+  int m = P_COULOMB;   // always refresh the source records (cheap, keeps them consistent)
+  if (short_range_on(ctx)) m |= P_CELLS;
+  return m;
+}
+
+template <class Real> void enqueue_step(depo_ctx *ctx, hipStream_t s) {
+  const State<Real> &st = state<Real>(ctx);
+  launch_prepare<Real>(st, ctx->ph, prepare_mode(ctx) | P_KICK_DRIFT, s);
+  enqueue_forces<Real>(ctx, s);
+  launch_finish<Real>(st, ctx->ph, F_KICK, s);
+}
+
+template <class Real> depo_status run_steps(depo_ctx *ctx, int n, hipStream_t s) {
+  if (n == 0) return DEPO_OK;
+  if (ctx->use_graph) {
+    if (!ctx->gexec) {
+      if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
+      enqueue_step<Real>(ctx, ctx->cap_stream);
+      hipError_t e = hipGetLastError();
+      hipError_t e2 = hipStreamEndCapture(ctx->cap_stream, &g);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return ctx->fail(DEPO_E_HIP, "step graph capture failed: %s",
+                         hipGetErrorString(e != hipSuccess ? e : e2));
+      }
+      hipError_t e3 = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e3 != hipSuccess) {
+        ctx->gexec = nullptr;
+        return ctx->fail(DEPO_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e3));
+      }
+    }
+    for (int k = 0; k < n; ++k) HIP_TRY(hipGraphLaunch(ctx->gexec, s));
+  } else {
+    for (int k = 0; k < n; ++k) enqueue_step<Real>(ctx, s);
+    HIP_TRY(hipGetLastError());
+  }
+  ctx->nstep += n;
+  return DEPO_OK;
+}
+
+template <class Real> depo_status run_steps_timed(depo_ctx *ctx, int n, hipStream_t s, double *ms) {
+  // phase boundaries: prepare | cell build | Coulomb | short range | finish
+  const State<Real> &st = state<Real>(ctx);
+  std::vector<hipEvent_t> ev(6 * (size_t)n, nullptr);
+  for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+  for (int k = 0; k < n; ++k) {
+    hipEvent_t *E = &ev[6 * (size_t)k];
+    HIP_TRY(hipEventRecord(E[0], s));
+    launch_prepare<Real>(st, ctx->ph, prepare_mode(ctx) | P_KICK_DRIFT, s);
+    HIP_TRY(hipEventRecord(E[1], s));
+    if (short_range_on(ctx)) launch_cells<Real>(st, ctx->ph, ctx->n_cells, (ctx->n_cells + 1023) / 1024, s);
+    HIP_TRY(hipEventRecord(E[2], s));
+    if (ctx->p.flags & DEPO_COULOMB) launch_coulomb<Real>(st, ctx->ph, ctx->n_tiles, ctx->ccfg, s);
+    HIP_TRY(hipEventRecord(E[3], s));
+    if (short_range_on(ctx)) launch_short_range<Real>(st, ctx->ph, s);
+    HIP_TRY(hipEventRecord(E[4], s));
+    launch_finish<Real>(st, ctx->ph, F_KICK, s);
+    HIP_TRY(hipEventRecord(E[5], s));
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int q = 0; q < 5; ++q) ms[q] = 0.0;
+  for (int k = 0; k < n; ++k)
+    for (int q = 0; q < 5; ++q) {
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, ev[6 * (size_t)k + q], ev[6 * (size_t)k + q + 1]));
+      ms[q] += t;
+    }
+  for (auto &e : ev) hipEventDestroy(e);
+  ctx->nstep += n;
+  return DEPO_OK;
+}
+
+template <class Real> depo_status do_init_field(depo_ctx *ctx, const double *h, hipStream_t s) {
+  using V4 = typename Prec<Real>::Vec4;
+  const size_t n = (size_t)ctx->nx * ctx->ny * ctx->nz;
+  std::vector<V4> tmp(n);
+  for (size_t k = 0; k < n; ++k) {
+    const double a = h[3 * k], b = h[3 * k + 1], c = h[3 * k + 2];
+    if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(c))
+      return ctx->fail(DEPO_E_INVALID, "field value %zu is not finite", k);
+    tmp[k].x = (Real)a; tmp[k].y = (Real)b; tmp[k].z = (Real)c; tmp[k].w = (Real)0;
+  }
+  HIP_TRY(hipMemcpyAsync(state<Real>(ctx).field, tmp.data(), n * sizeof(V4), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return DEPO_OK;
+}
+
+depo_status build_samples(depo_ctx *ctx, const depo_sample_params *sp, const double *h_d) {
+  const depo_params &p = ctx->p;
+  ctx->samples.assign(ctx->S, SampleDev{});
+  double dmax_all = 0.0;
+  int64_t cells = 0;
+  for (int s = 0; s < ctx->S; ++s) {
+    SampleDev &sd = ctx->samples[s];
+    const int64_t b = ctx->off[s], e = ctx->off[s + 1];
+    sd.start = (int32_t)b;
+    sd.count = (int32_t)(e - b);
+    sd.charge_scale = sp[s].charge_scale;
+    sd.hamaker = sp[s].hamaker;
+    sd.temperature = sp[s].temperature;
+    double dmax = 0.0;
+    for (int64_t i = b; i < e; ++i) dmax = std::max(dmax, h_d[i]);
+    dmax_all = std::max(dmax_all, dmax);
+    const double reach = 1.25 * dmax;   // largest centre distance with a short-range force
+    if (reach * 3.0 > p.L) return ctx->fail(DEPO_E_INVALID, "sample %d: particles too large for L", s);
+    const double ns = (double)std::max<int64_t>(e - b, 1);
+    double h = std::max(reach, std::cbrt(4.0 * p.R * p.R * p.L / ns));
+    const int64_t cap = (e - b) + 64;
+    int ncx, ncy;
+    for (;;) {
+      ncx = std::max(3, (int)std::floor(p.L / h));
+      ncy = std::max(1, (int)std::floor(2.0 * p.R / h));
+      if ((int64_t)ncx * ncy * ncy <= cap) break;
+      h *= 1.05;
+    }
+    sd.ncx = ncx;
+    sd.ncy = ncy;
+    sd.ncz = ncy;
+    sd.cell_base = (int32_t)cells;
+    cells += (int64_t)ncx * ncy * ncy;
+  }
+  if (cells > ctx->cell_cap) return ctx->fail(DEPO_E_CAPACITY, "cell grid exceeds reserved capacity");
+  ctx->n_cells = (int)cells;
+  const double dq = dmax_all * ctx->ph.inv_ux;
+  ctx->ph.near2 = dq * dq;
+  return DEPO_OK;
+}
+
+template <class Real>
+depo_status do_seed(depo_ctx *ctx, const depo_sample_params *sp, const double *hx, const double *hv,
+                    const double *hd, const double *hq, hipStream_t s) {
+  using Pos = typename Prec<Real>::Pos;
+  using SPos = typename Prec<Real>::SPos;
+  const depo_params &p = ctx->p;
+  const int64_t N = ctx->N;
+  const int B = ctx->fp64() ? 64 : 32;
+  for (int k = 0; k < ctx->S; ++k) {
+    if (!std::isfinite(sp[k].charge_scale) || !std::isfinite(sp[k].hamaker) || sp[k].hamaker < 0.0 ||
+        !std::isfinite(sp[k].temperature))
+      return ctx->fail(DEPO_E_INVALID, "sample %d: parameters must be finite, hamaker >= 0", k);
+  }
+  std::vector<Pos> px(N), py(N), pz(N);
+  std::vector<int32_t> sid(N), zeros_i(N, 0);
+  std::vector<double> zeros_d(N, 0.0);
+  for (int k = 0; k < ctx->S; ++k)
+    for (int64_t i = ctx->off[k]; i < ctx->off[k + 1]; ++i) sid[i] = k;
+  for (int64_t i = 0; i < N; ++i) {
+    const double x = hx[3 * i], y = hx[3 * i + 1], z = hx[3 * i + 2];
+    if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z))
+      return ctx->fail(DEPO_E_INVALID, "particle %lld: position not finite", (long long)i);
+    if (y * y + z * z >= p.R * p.R)
+      return ctx->fail(DEPO_E_INVALID, "particle %lld: outside the pipe", (long long)i);
+    if (!(hd[i] > 0.0) || !(hd[i] < 0.25 * p.R) || !std::isfinite(hq[i]))
+      return ctx->fail(DEPO_E_INVALID, "particle %lld: diameter must be in (0, R/4), charge finite", (long long)i);
+    double fx = std::fmod(x, p.L) / p.L;
+    if (fx < 0.0) fx += 1.0;
+    const double sc = std::ldexp(fx, B);
+    const double lim = std::ldexp(1.0, B);
+    if constexpr (sizeof(Pos) == 4) {
+      px[i] = (Pos)(uint64_t)std::llround(sc >= lim ? 0.0 : sc);
+    } else {
+      px[i] = sc >= lim ? (Pos)0 : (Pos)sc;
+    }
+    py[i] = (Pos)(SPos)std::llround(y * ctx->ph.inv_ur);
+    pz[i] = (Pos)(SPos)std::llround(z * ctx->ph.inv_ur);
+    if (hv) {
+      for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(hv[3 * i + c]))
+          return ctx->fail(DEPO_E_INVALID, "particle %lld: velocity not finite", (long long)i);
+    }
+  }
+  depo_status stt = build_samples(ctx, sp, hd);
+  if (stt != DEPO_OK) return stt;
+  ctx->sp.assign(sp, sp + ctx->S);
+  ctx->ph.N = (int32_t)N;
+  State<Real> &st = state<Real>(ctx);
+  std::vector<TileDev> tiles;
+  build_tiles(ctx, tiles);
+  ctx->n_tiles = (int)tiles.size();
+  const size_t nb = (size_t)N;
+  HIP_TRY(hipMemcpyAsync(st.px, px.data(), nb * sizeof(Pos), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(st.py, py.data(), nb * sizeof(Pos), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(st.pz, pz.data(), nb * sizeof(Pos), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(st.d, hd, nb * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(st.qb, hq, nb * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(st.ell, zeros_d.data(), nb * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(st.dep, zeros_i.data(), nb * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(st.sid, sid.data(), nb * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(st.nbr, zeros_i.data(), nb * 4, hipMemcpyHostToDevice, s));
+  std::vector<Real> vbuf;
+  if (hv) {
+    vbuf.resize(nb);
+    Real *dst[3] = {st.vx, st.vy, st.vz};
+    for (int c = 0; c < 3; ++c) {
+      for (size_t i = 0; i < nb; ++i) vbuf[i] = (Real)hv[3 * i + c];
+      HIP_TRY(hipMemcpyAsync(dst[c], vbuf.data(), nb * sizeof(Real), hipMemcpyHostToDevice, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(st.samples, ctx->samples.data(), ctx->S * sizeof(SampleDev), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(st.tiles, tiles.data(), tiles.size() * sizeof(TileDev), hipMemcpyHostToDevice, s));
+  const int32_t zero[16] = {0};
+  HIP_TRY(hipMemcpyAsync(st.nstep, zero, 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(st.err, zero, 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  // initial force evaluation at x^0 (and v^0 = u_f(x^0) when no velocity is given)
+  launch_prepare<Real>(st, ctx->ph, prepare_mode(ctx) | P_SEED, s);
+  enqueue_forces<Real>(ctx, s);
+  launch_finish<Real>(st, ctx->ph, hv ? 0 : F_V_FROM_FLUID, s);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  ctx->nstep = 0;
+  ctx->seeded = true;
+  ctx->drop_graph();
+  return DEPO_OK;
+}
+
+template <class Real> depo_status check_err(depo_ctx *ctx, hipStream_t s) {
+  uint32_t e = 0;
+  HIP_TRY(hipMemcpyAsync(&e, state<Real>(ctx).err, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (e & ERR_NONFINITE) return ctx->fail(DEPO_E_NONFINITE, "a velocity or acceleration became non-finite");
+  return DEPO_OK;
+}
+
+template <class Real>
+depo_status do_read(depo_ctx *ctx, double *hx, double *hv, double *ha, int32_t *hdep, int32_t *hnb, hipStream_t s) {
+  using Pos = typename Prec<Real>::Pos;
+  const State<Real> &st = state<Real>(ctx);
+  const size_t N = (size_t)ctx->N;
+  if (hx) {
+    std::vector<Pos> p(3 * N);
+    HIP_TRY(hipMemcpyAsync(p.data(), st.px, N * sizeof(Pos), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(p.data() + N, st.py, N * sizeof(Pos), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(p.data() + 2 * N, st.pz, N * sizeof(Pos), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (size_t i = 0; i < N; ++i) {
+      hx[3 * i] = (double)p[i] * ctx->ph.ux;
+      if constexpr (sizeof(Pos) == 4) {
+        hx[3 * i + 1] = (double)(int32_t)p[N + i] * ctx->ph.ur;
+        hx[3 * i + 2] = (double)(int32_t)p[2 * N + i] * ctx->ph.ur;
+      } else {
+        hx[3 * i + 1] = (double)(int64_t)p[N + i] * ctx->ph.ur;
+        hx[3 * i + 2] = (double)(int64_t)p[2 * N + i] * ctx->ph.ur;
+      }
+    }
+  }
+  auto vec3 = [&](double *h, Real *a, Real *b, Real *c) -> depo_status {
+    std::vector<Real> t(3 * N);
+    HIP_TRY(hipMemcpyAsync(t.data(), a, N * sizeof(Real), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(t.data() + N, b, N * sizeof(Real), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(t.data() + 2 * N, c, N * sizeof(Real), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (size_t i = 0; i < N; ++i)
+      for (int k = 0; k < 3; ++k) h[3 * i + k] = (double)t[k * N + i];
+    return DEPO_OK;
+  };
+  depo_status r;
+  if (hv && (r = vec3(hv, st.vx, st.vy, st.vz)) != DEPO_OK) return r;
+  if (ha && (r = vec3(ha, st.ax, st.ay, st.az)) != DEPO_OK) return r;
+  if (hdep) HIP_TRY(hipMemcpyAsync(hdep, st.dep, N * 4, hipMemcpyDeviceToHost, s));
+  if (hnb) HIP_TRY(hipMemcpyAsync(hnb, st.nbr, N * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return check_err<Real>(ctx, s);
+}
+
+template <class Real> depo_status do_tally(depo_ctx *ctx, depo_tally *out, hipStream_t s) {
+  const State<Real> &st = state<Real>(ctx);
+  launch_tally<Real>(st, ctx->ph, ctx->nstep, s);
+  HIP_TRY(hipGetLastError());
+  std::vector<double> t((size_t)ctx->S * 8);
+  HIP_TRY(hipMemcpyAsync(t.data(), st.tally, t.size() * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const double us = ctx->p.re_tau * ctx->p.nu / ctx->p.R;
+  for (int k = 0; k < ctx->S; ++k) {
+    const double *r = &t[(size_t)k * 8];
+    depo_tally &o = out[k];
+    o.m_dep = r[0];
+    o.n_dep = (int64_t)std::llround(r[1]);
+    o.m_alive_dt = r[2] * ctx->p.dt;
+    o.t = ctx->nstep * ctx->p.dt;
+    o.v_dep = o.m_alive_dt > 0.0 ? 0.5 * ctx->p.R * o.m_dep / o.m_alive_dt : 0.0;
+    o.v_dep_plus = o.v_dep / us;
+    o.v_dep_se = o.m_dep > 0.0 ? o.v_dep * std::sqrt(r[3]) / o.m_dep : 0.0;
+    o.j_soft = r[4];
+    o.n_alive = (int64_t)std::llround(r[5]);
+  }
+  return check_err<Real>(ctx, s);
+}
+
+// checkpoint payload: positions, velocities, accelerations, fluid velocities,
+// d, qbase, ell, dep, per-sample parameters
+template <class Real> size_t blob_payload(const depo_ctx *ctx) {
+  const size_t N = (size_t)ctx->N;
+  return N * (3 * sizeof(typename Prec<Real>::Pos) + 9 * sizeof(Real) + 3 * 8 + 4) +
+         (size_t)ctx->S * sizeof(depo_sample_params);
+}
+
+template <class Real> depo_status do_download(depo_ctx *ctx, void *blob, size_t bytes, hipStream_t s) {
+  using Pos = typename Prec<Real>::Pos;
+  const State<Real> &st = state<Real>(ctx);
+  const size_t N = (size_t)ctx->N;
+  const size_t pay = blob_payload<Real>(ctx);
+  if (bytes != sizeof(BlobHeader) + pay) return ctx->fail(DEPO_E_INVALID, "blob size must be %zu", sizeof(BlobHeader) + pay);
+  char *p = (char *)blob + sizeof(BlobHeader);
+  auto get = [&](const void *src, size_t n) -> depo_status {
+    HIP_TRY(hipMemcpyAsync(p, src, n, hipMemcpyDeviceToHost, s));
+    p += n;
+    return DEPO_OK;
+  };
+  depo_status r;
+  for (const Pos *a : {st.px, st.py, st.pz})
+    if ((r = get(a, N * sizeof(Pos))) != DEPO_OK) return r;
+  for (const Real *a : {st.vx, st.vy, st.vz, st.ax, st.ay, st.az, st.ux, st.uy, st.uz})
+    if ((r = get(a, N * sizeof(Real))) != DEPO_OK) return r;
+  for (const double *a : {st.d, st.qb, st.ell})
+    if ((r = get(a, N * 8)) != DEPO_OK) return r;
+  if ((r = get(st.dep, N * 4)) != DEPO_OK) return r;
+  HIP_TRY(hipStreamSynchronize(s));
+  std::memcpy(p, ctx->sp.data(), ctx->S * sizeof(depo_sample_params));
+  BlobHeader h{};
+  std::memcpy(h.magic, "DEPOCKPT", 8);
+  h.version = 1;
+  h.real_bytes = (uint32_t)ctx->p.real_bytes;
+  h.n = ctx->N;
+  h.s = ctx->S;
+  h.nstep = ctx->nstep;
+  h.payload = pay;
+  h.crc = crc32_update(0, (const char *)blob + sizeof(BlobHeader), pay);
+  std::memcpy(blob, &h, sizeof h);
+  return check_err<Real>(ctx, s);
+}
+
+template <class Real> depo_status do_upload(depo_ctx *ctx, const void *blob, size_t bytes, hipStream_t s) {
+  using Pos = typename Prec<Real>::Pos;
+  const State<Real> &st = state<Real>(ctx);
+  const size_t N = (size_t)ctx->N;
+  const size_t pay = blob_payload<Real>(ctx);
+  if (bytes != sizeof(BlobHeader) + pay) return ctx->fail(DEPO_E_CORRUPT, "blob size mismatch");
+  BlobHeader h;
+  std::memcpy(&h, blob, sizeof h);
+  if (std::memcmp(h.magic, "DEPOCKPT", 8) != 0 || h.version != 1 || h.real_bytes != (uint32_t)ctx->p.real_bytes ||
+      h.n != ctx->N || h.s != ctx->S || h.payload != pay || h.nstep < 0)
+    return ctx->fail(DEPO_E_CORRUPT, "blob header does not match this context");
+  const char *p = (const char *)blob + sizeof(BlobHeader);
+  if (crc32_update(0, p, pay) != h.crc) return ctx->fail(DEPO_E_CORRUPT, "blob CRC mismatch");
+  // per-sample parameters and diameters rebuild the sample table
+  const char *q = p + N * (3 * sizeof(Pos) + 9 * sizeof(Real));
+  std::vector<double> d(N);
+  std::memcpy(d.data(), q, N * 8);
+  std::vector<depo_sample_params> sp(ctx->S);
+  std::memcpy(sp.data(), p + pay - ctx->S * sizeof(depo_sample_params), ctx->S * sizeof(depo_sample_params));
+  depo_status r = build_samples(ctx, sp.data(), d.data());
+  if (r != DEPO_OK) return r;
+  ctx->sp = sp;
+  auto put = [&](void *dst, size_t n) -> depo_status {
+    HIP_TRY(hipMemcpyAsync(dst, p, n, hipMemcpyHostToDevice, s));
+    p += n;
+    return DEPO_OK;
+  };
+  for (Pos *a : {st.px, st.py, st.pz})
+    if ((r = put(a, N * sizeof(Pos))) != DEPO_OK) return r;
+  for (Real *a : {st.vx, st.vy, st.vz, st.ax, st.ay, st.az, st.ux, st.uy, st.uz})
+    if ((r = put(a, N * sizeof(Real))) != DEPO_OK) return r;
+  for (double *a : {st.d, st.qb, st.ell})
+    if ((r = put(a, N * 8)) != DEPO_OK) return r;
+  if ((r = put(st.dep, N * 4)) != DEPO_OK) return r;
+  HIP_TRY(hipMemcpyAsync(st.samples, ctx->samples.data(), ctx->S * sizeof(SampleDev), hipMemcpyHostToDevice, s));
+  const int32_t ns = h.nstep;
+  HIP_TRY(hipMemcpyAsync(st.nstep, &ns, 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  // refresh the Coulomb source radii
+  launch_prepare<Real>(st, ctx->ph, P_SEED | P_COULOMB, s);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  ctx->nstep = h.nstep;
+  ctx->seeded = true;
+  ctx->drop_graph();
+  return DEPO_OK;
+}
+
+}  // namespace
+
+#define DISPATCH(fn, ...) (ctx->fp64() ? fn<double>(__VA_ARGS__) : fn<float>(__VA_ARGS__))
+
+extern "C" {
+
+const char *depo_status_string(int status) {
+  switch (status) {
+    case DEPO_OK: return "DEPO_OK";
+    case DEPO_E_INVALID: return "DEPO_E_INVALID";
+    case DEPO_E_STATE: return "DEPO_E_STATE";
+    case DEPO_E_HIP: return "DEPO_E_HIP";
+    case DEPO_E_NONFINITE: return "DEPO_E_NONFINITE";
+    case DEPO_E_CAPACITY: return "DEPO_E_CAPACITY";
+    case DEPO_E_CORRUPT: return "DEPO_E_CORRUPT";
+    default: return "DEPO_E_UNKNOWN";
+  }
+}
+
+depo_status depo_create(const depo_params *p, depo_ctx **out) {
+  if (!out) return DEPO_E_INVALID;
+  *out = nullptr;
+  if (!p) return DEPO_E_INVALID;
+  const bool ok = finite_pos(p->R) && finite_pos(p->L) && finite_pos(p->nu) && finite_pos(p->rho_f) &&
+                  finite_pos(p->rho_p) && finite_pos(p->dt) && finite_pos(p->re_tau) && finite_pos(p->e_pp) &&
+                  p->e_pp <= 1.0 && p->tau_col_steps >= 1 && (p->real_bytes == 4 || p->real_bytes == 8) &&
+                  finite_pos(p->delta_min) && finite_pos(p->kr_over_k) && finite_pos(p->eps0) &&
+                  std::isfinite(p->g_body[0]) && std::isfinite(p->g_body[1]) && std::isfinite(p->g_body[2]) &&
+                  finite_pos(p->E_young) && finite_pos(p->delta_c) && std::isfinite(p->acont_coef) &&
+                  p->acont_coef >= 0.0 && (p->flags & ~kKnownFlags) == 0 && p->reserved == 0 &&
+                  (!(p->flags & DEPO_SOFT_TALLY) || (finite_pos(p->soft_eps) && finite_pos(p->soft_tau)));
+  if (!ok) return DEPO_E_INVALID;
+  depo_ctx *ctx = new depo_ctx();
+  ctx->p = *p;
+  if (ctx->fp64()) ctx->ccfg = CoulombConfig{1, 4, 16};
+  fill_phys(ctx);
+  *out = ctx;
+  return DEPO_OK;
+}
+
+void depo_destroy(depo_ctx *ctx) {
+  if (!ctx) return;
+  ctx->drop_graph();
+  if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+  delete ctx;
+}
+
+const char *depo_last_error(const depo_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+depo_status depo_set_layout(depo_ctx *ctx, int32_t n_samples, const int64_t *offsets, int32_t nx, int32_t ny,
+                            int32_t nz) {
+  if (!ctx) return DEPO_E_INVALID;
+  if (n_samples < 1 || !offsets) return ctx->fail(DEPO_E_INVALID, "need n_samples >= 1 and offsets");
+  if (offsets[0] != 0) return ctx->fail(DEPO_E_INVALID, "offsets[0] must be 0");
+  for (int s = 0; s < n_samples; ++s)
+    if (offsets[s + 1] < offsets[s]) return ctx->fail(DEPO_E_INVALID, "offsets must be non-decreasing");
+  if (offsets[n_samples] > kMaxN) return ctx->fail(DEPO_E_INVALID, "at most 2^26 particles");
+  for (int v : {nx, ny, nz})
+    if (v < 4 || v > 4096) return ctx->fail(DEPO_E_INVALID, "field grid must be 4..4096 nodes per axis");
+  ctx->drop_graph();
+  ctx->has_layout = true;
+  ctx->bound = ctx->field_ready = ctx->seeded = false;
+  ctx->ws = nullptr;
+  ctx->S = n_samples;
+  ctx->off.assign(offsets, offsets + n_samples + 1);
+  ctx->N = offsets[n_samples];
+  ctx->nx = nx;
+  ctx->ny = ny;
+  ctx->nz = nz;
+  ctx->cell_cap = ctx->N + 64LL * n_samples;
+  ctx->scan_blocks = (int)((ctx->cell_cap + 1023) / 1024);
+  int tiles = 0;
+  for (int s = 0; s < n_samples; ++s) tiles += (int)((offsets[s + 1] - offsets[s] + 63) / 64);
+  ctx->tile_cap = tiles;
+  fill_phys(ctx);
+  ctx->ws_need = ctx->fp64() ? carve<double>(ctx, nullptr, ctx->sd) : carve<float>(ctx, nullptr, ctx->sf);
+  return DEPO_OK;
+}
+
+depo_status depo_workspace_bytes(const depo_ctx *ctx, size_t *bytes) {
+  if (!ctx || !bytes) return DEPO_E_INVALID;
+  if (!ctx->has_layout) return DEPO_E_STATE;
+  *bytes = ctx->ws_need;
+  return DEPO_OK;
+}
+
+depo_status depo_bind(depo_ctx *ctx, void *d_work, size_t bytes) {
+  if (!ctx) return DEPO_E_INVALID;
+  if (!ctx->has_layout) return ctx->fail(DEPO_E_STATE, "set the layout before binding");
+  if (!d_work || ((uintptr_t)d_work % kAlign) != 0) return ctx->fail(DEPO_E_INVALID, "workspace must be 256-byte aligned");
+  if (bytes < ctx->ws_need) return ctx->fail(DEPO_E_CAPACITY, "workspace needs %zu bytes", ctx->ws_need);
+  ctx->drop_graph();
+  ctx->ws = (char *)d_work;
+  if (ctx->fp64()) carve<double>(ctx, ctx->ws, ctx->sd); else carve<float>(ctx, ctx->ws, ctx->sf);
+  int32_t *counts = ctx->fp64() ? ctx->sd.cell_count : ctx->sf.cell_count;
+  launch_clear_int(counts, (size_t)ctx->cell_cap, nullptr);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(nullptr));
+  ctx->bound = true;
+  ctx->field_ready = ctx->seeded = false;
+  return DEPO_OK;
+}
+
+depo_status depo_init_field(depo_ctx *ctx, const double *h_uvw, depo_stream stream) {
+  if (!ctx) return DEPO_E_INVALID;
+  if (!ctx->bound) return ctx->fail(DEPO_E_STATE, "bind a workspace first");
+  if (!h_uvw) return ctx->fail(DEPO_E_INVALID, "null field");
+  depo_status r = DISPATCH(do_init_field, ctx, h_uvw, (hipStream_t)stream);
+  if (r == DEPO_OK) ctx->field_ready = true;
+  return r;
+}
+
+depo_status depo_seed(depo_ctx *ctx, const depo_sample_params *sp, const double *h_x3, const double *h_v3,
+                      const double *h_d, const double *h_qbase, depo_stream stream) {
+  if (!ctx) return DEPO_E_INVALID;
+  if (!ctx->bound || !ctx->field_ready) return ctx->fail(DEPO_E_STATE, "bind a workspace and upload the field first");
+  if (!sp || (ctx->N > 0 && (!h_x3 || !h_d || !h_qbase))) return ctx->fail(DEPO_E_INVALID, "null input array");
+  ctx->seeded = false;
+  return DISPATCH(do_seed, ctx, sp, h_x3, h_v3, h_d, h_qbase, (hipStream_t)stream);
+}
+
+depo_status depo_set_sample_params(depo_ctx *ctx, const depo_sample_params *sp, depo_stream stream) {
+  if (!ctx) return DEPO_E_INVALID;
+  if (!ctx->seeded) return ctx->fail(DEPO_E_STATE, "seed first");
+  if (!sp) return ctx->fail(DEPO_E_INVALID, "null sample parameters");
+  for (int k = 0; k < ctx->S; ++k) {
+    if (!std::isfinite(sp[k].charge_scale) || !std::isfinite(sp[k].hamaker) || sp[k].hamaker < 0.0 ||
+        !std::isfinite(sp[k].temperature))
+      return ctx->fail(DEPO_E_INVALID, "sample %d: parameters must be finite, hamaker >= 0", k);
+  }
+  for (int k = 0; k < ctx->S; ++k) {
+    ctx->samples[k].charge_scale = sp[k].charge_scale;
+    ctx->samples[k].hamaker = sp[k].hamaker;
+    ctx->samples[k].temperature = sp[k].temperature;
+  }
+  ctx->sp.assign(sp, sp + ctx->S);
+  SampleDev *dst = ctx->fp64() ? ctx->sd.samples : ctx->sf.samples;
+  HIP_TRY(hipMemcpyAsync(dst, ctx->samples.data(), ctx->S * sizeof(SampleDev), hipMemcpyHostToDevice,
+                         (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  return DEPO_OK;
+}
+
+depo_status depo_step(depo_ctx *ctx, int32_t n_steps, depo_stream stream) {
+  if (!ctx) return DEPO_E_INVALID;
+  if (!ctx->seeded) return ctx->fail(DEPO_E_STATE, "seed first");
+  if (n_steps < 0) return ctx->fail(DEPO_E_INVALID, "n_steps must be >= 0");
+  if ((int64_t)ctx->nstep + n_steps > (int64_t)INT32_MAX - 1) return ctx->fail(DEPO_E_INVALID, "step counter overflow");
+  return DISPATCH(run_steps, ctx, n_steps, (hipStream_t)stream);
+}
+
+depo_status depo_step_timed(depo_ctx *ctx, int32_t n_steps, depo_stream stream, double *h_phase_ms) {
+  if (!ctx) return DEPO_E_INVALID;
+  if (!ctx->seeded) return ctx->fail(DEPO_E_STATE, "seed first");
+  if (n_steps < 1 || n_steps > 100000 || !h_phase_ms) return ctx->fail(DEPO_E_INVALID, "need 1..100000 steps and an output array");
+  if ((int64_t)ctx->nstep + n_steps > (int64_t)INT32_MAX - 1) return ctx->fail(DEPO_E_INVALID, "step counter overflow");
+  return DISPATCH(run_steps_timed, ctx, n_steps, (hipStream_t)stream, h_phase_ms);
+}
+
+depo_status depo_set_kernel_config(depo_ctx *ctx, int32_t targets_per_lane, int32_t waves, int32_t block,
+                                   int32_t use_graph) {
+  if (!ctx) return DEPO_E_INVALID;
+  CoulombConfig c{targets_per_lane, waves, block};
+  if (!coulomb_config_supported(ctx->p.real_bytes, c))
+    return ctx->fail(DEPO_E_INVALID, "unsupported pair-kernel configuration (%d, %d, %d)", targets_per_lane, waves, block);
+  ctx->ccfg = c;
+  ctx->use_graph = use_graph != 0;
+  ctx->drop_graph();
+  if (ctx->seeded) {
+    std::vector<TileDev> tiles;
+    build_tiles(ctx, tiles);
+    ctx->n_tiles = (int)tiles.size();
+    TileDev *dst = ctx->fp64() ? ctx->sd.tiles : ctx->sf.tiles;
+    HIP_TRY(hipMemcpy(dst, tiles.data(), tiles.size() * sizeof(TileDev), hipMemcpyHostToDevice));
+  }
+  return DEPO_OK;
+}
+
+depo_status depo_eval_accel(depo_ctx *ctx, depo_stream stream) {
+  if (!ctx) return DEPO_E_INVALID;
+  if (!ctx->seeded) return ctx->fail(DEPO_E_STATE, "seed first");
+  hipStream_t s = (hipStream_t)stream;
+  if (ctx->fp64()) {
+    launch_prepare<double>(ctx->sd, ctx->ph, prepare_mode(ctx), s);
+    enqueue_forces<double>(ctx, s);
+    launch_finish<double>(ctx->sd, ctx->ph, 0, s);
+  } else {
+    launch_prepare<float>(ctx->sf, ctx->ph, prepare_mode(ctx), s);
+    enqueue_forces<float>(ctx, s);
+    launch_finish<float>(ctx->sf, ctx->ph, 0, s);
+  }
+  HIP_TRY(hipGetLastError());
+  return DEPO_OK;
+}
+
+depo_status depo_read_particles(depo_ctx *ctx, double *h_x3, double *h_v3, double *h_a3, int32_t *h_dep_step,
+                                int32_t *h_neighbours, depo_stream stream) {
+  if (!ctx) return DEPO_E_INVALID;
+  if (!ctx->seeded) return ctx->fail(DEPO_E_STATE, "seed first");
+  return DISPATCH(do_read, ctx, h_x3, h_v3, h_a3, h_dep_step, h_neighbours, (hipStream_t)stream);
+}
+
+depo_status depo_tally_read(depo_ctx *ctx, depo_tally *out, depo_stream stream) {
+  if (!ctx) return DEPO_E_INVALID;
+  if (!ctx->seeded) return ctx->fail(DEPO_E_STATE, "seed first");
+  if (!out) return ctx->fail(DEPO_E_INVALID, "null output");
+  return DISPATCH(do_tally, ctx, out, (hipStream_t)stream);
+}
+
+depo_status depo_state_bytes(const depo_ctx *ctx, size_t *bytes) {
+  if (!ctx || !bytes) return DEPO_E_INVALID;
+  if (!ctx->has_layout) return DEPO_E_STATE;
+  *bytes = sizeof(BlobHeader) + (ctx->fp64() ? blob_payload<double>(ctx) : blob_payload<float>(ctx));
+  return DEPO_OK;
+}
+
+depo_status depo_state_download(depo_ctx *ctx, void *h_blob, size_t bytes, depo_stream stream) {
+  if (!ctx) return DEPO_E_INVALID;
+  if (!ctx->seeded) return ctx->fail(DEPO_E_STATE, "seed first");
+  if (!h_blob) return ctx->fail(DEPO_E_INVALID, "null blob");
+  return DISPATCH(do_download, ctx, h_blob, bytes, (hipStream_t)stream);
+}
+
+depo_status depo_state_upload(depo_ctx *ctx, const void *h_blob, size_t bytes, depo_stream stream) {
+  if (!ctx) return DEPO_E_INVALID;
+  if (!ctx->bound || !ctx->field_ready) return ctx->fail(DEPO_E_STATE, "bind a workspace and upload the field first");
+  if (!h_blob) return ctx->fail(DEPO_E_INVALID, "null blob");
+  return DISPATCH(do_upload, ctx, h_blob, bytes, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,34 @@
+// Host-side launchers of the device kernels (one translation unit per kernel family).
+#pragma once
+
+#include "common.hpp"
+
+namespace depo {
+
+// k_prepare modes
+enum : int { P_KICK_DRIFT = 1, P_COULOMB = 2, P_CELLS = 4, P_SEED = 8 };
+// k_finish modes
+enum : int { F_KICK = 1, F_V_FROM_FLUID = 2 };
+
+template <class Real> void launch_prepare(const State<Real> &st, const Phys &ph, int mode, hipStream_t s);
+template <class Real> void launch_finish(const State<Real> &st, const Phys &ph, int mode, hipStream_t s);
+template <class Real> void launch_tally(const State<Real> &st, const Phys &ph, int nstep, hipStream_t s);
+
+// Cell list: scan of the histogram, scatter, in-cell ordering, short-range forces.
+template <class Real>
+void launch_cells(const State<Real> &st, const Phys &ph, int n_cells, int n_scan_blocks, hipStream_t s);
+template <class Real> void launch_short_range(const State<Real> &st, const Phys &ph, hipStream_t s);
+void launch_clear_int(int32_t *p, size_t n, hipStream_t s);
+
+// Coulomb pair sums.
+struct CoulombConfig {
+  int ipl;     // targets per lane
+  int waves;   // waves per workgroup (split the source range)
+  int block;   // sources per compensated block
+};
+template <class Real>
+void launch_coulomb(const State<Real> &st, const Phys &ph, int n_tiles, const CoulombConfig &cfg, hipStream_t s);
+int coulomb_tile_targets(const CoulombConfig &cfg);
+bool coulomb_config_supported(int real_bytes, const CoulombConfig &cfg);
+
+}  // namespace depo

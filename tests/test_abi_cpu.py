@@ -1,0 +1,140 @@
+"""C-ABI contract tests that need no GPU: the library loads, exports every
+entry point declared in include/depo.h, and validates arguments on the host."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from synthetic.workloads import physical_params
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def depo():
+    from paper_2205_04979_amd import depo as d
+    if not os.path.exists(d.library_path()):
+        from paper_2205_04979_amd.build import build
+        build()
+    d.lib()
+    return d
+
+
+def declared_entry_points():
+    src = open(os.path.join(ROOT, "include", "depo.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:depo_status|void|const char \*)\s*(depo_[a-z_]+)\(", src, re.M)))
+
+
+def test_every_declared_symbol_is_exported(depo):
+    names = declared_entry_points()
+    assert len(names) >= 18
+    h = C.CDLL(depo.library_path())
+    for n in names:
+        assert hasattr(h, n), n
+    assert sorted(depo.EXPORTED) == names
+
+
+def test_struct_layouts_match_header(depo, tmp_path):
+    """sizeof/offsetof of the C structs, as gcc lays them out from include/depo.h, equal the ctypes mirror."""
+    import subprocess
+    checks = []
+    for cname, py in (("depo_params", depo.Params), ("depo_sample_params", depo.SampleParams),
+                      ("depo_tally", depo.Tally)):
+        checks.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            checks.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "depo.h"\nint main(void){' + "".join(checks)
+                   + "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                      check=True).stdout.splitlines())
+    for cname, py in (("depo_params", depo.Params), ("depo_sample_params", depo.SampleParams),
+                      ("depo_tally", depo.Tally)):
+        assert int(got[cname]) == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+def test_status_strings(depo):
+    L = depo.lib()
+    for code, name in [(0, b"DEPO_OK"), (-1, b"DEPO_E_INVALID"), (-4, b"DEPO_E_NONFINITE"), (-6, b"DEPO_E_CORRUPT")]:
+        assert L.depo_status_string(code) == name
+    assert L.depo_status_string(99) == b"DEPO_E_UNKNOWN"
+
+
+@pytest.mark.parametrize("key,value", [("R", 0.0), ("L", -1.0), ("nu", float("nan")), ("dt", 0.0),
+                                       ("e_pp", 1.5), ("tau_col_steps", 0), ("eps0", float("inf"))])
+def test_create_rejects_bad_params(depo, key, value):
+    p = physical_params()
+    p[key] = value
+    with pytest.raises(depo.DepoError) as ei:
+        depo.Context(p)
+    assert ei.value.status == depo.E_INVALID
+
+
+def test_create_rejects_bad_precision_and_flags(depo):
+    L = depo.lib()
+    cp = depo.make_params(physical_params(), 4)
+    h = C.c_void_p()
+    cp.real_bytes = 2
+    assert L.depo_create(C.byref(cp), C.byref(h)) == depo.E_INVALID and not h
+    cp.real_bytes = 8
+    cp.flags |= 1 << 20
+    assert L.depo_create(C.byref(cp), C.byref(h)) == depo.E_INVALID
+    cp.flags &= (1 << 10) - 1
+    cp.reserved = 1
+    assert L.depo_create(C.byref(cp), C.byref(h)) == depo.E_INVALID
+    assert L.depo_create(None, C.byref(h)) == depo.E_INVALID
+
+
+def test_layout_validation_and_workspace_size(depo):
+    ctx = depo.Context(physical_params(), 4)
+    with pytest.raises(depo.DepoError):
+        ctx.set_layout([0, 10, 5], 16, 16, 16)           # decreasing offsets
+    with pytest.raises(depo.DepoError):
+        ctx.set_layout([1, 10], 16, 16, 16)               # offsets[0] != 0
+    with pytest.raises(depo.DepoError):
+        ctx.set_layout([0, 10], 3, 16, 16)                # grid too small
+    with pytest.raises(depo.DepoError):
+        ctx.set_layout([0, 1 << 27], 16, 16, 16)          # too many particles
+    ctx.set_layout([0, 1000], 16, 16, 16)
+    small = ctx.workspace_bytes()
+    ctx.set_layout([0, 100000], 16, 16, 16)
+    big = ctx.workspace_bytes()
+    assert big > small > 16 ** 3 * 16
+    # FP32 state is at least ~150 B per particle, FP64 more
+    assert (big - small) / 99000 > 100
+    ctx64 = depo.Context(physical_params(), 8)
+    ctx64.set_layout([0, 100000], 16, 16, 16)
+    assert ctx64.workspace_bytes() > big
+
+
+def test_calls_out_of_order_are_state_errors(depo):
+    L = depo.lib()
+    ctx = depo.Context(physical_params(), 4)
+    n = C.c_size_t()
+    assert L.depo_workspace_bytes(ctx._h, C.byref(n)) == depo.E_STATE
+    assert L.depo_step(ctx._h, 1, None) == depo.E_STATE
+    assert L.depo_bind(ctx._h, C.c_void_p(256), 1 << 20) == depo.E_STATE
+    ctx.set_layout([0, 100], 8, 8, 8)
+    assert L.depo_bind(ctx._h, C.c_void_p(255), 1 << 30) == depo.E_INVALID     # misaligned
+    assert L.depo_bind(ctx._h, C.c_void_p(256), 16) == depo.E_CAPACITY          # too small
+    assert L.depo_seed(ctx._h, None, None, None, None, None, None) == depo.E_STATE
+    assert L.depo_tally_read(ctx._h, None, None) == depo.E_STATE
+    assert L.depo_state_upload(ctx._h, None, 0, None) == depo.E_STATE
+    assert b"bind" in L.depo_last_error(ctx._h)
+
+
+def test_kernel_config_validation(depo):
+    ctx = depo.Context(physical_params(), 4)
+    L = depo.lib()
+    assert L.depo_set_kernel_config(ctx._h, 3, 8, 32, 1) == depo.E_INVALID
+    assert L.depo_set_kernel_config(ctx._h, 2, 8, 32, 1) == depo.OK
+    ctx64 = depo.Context(physical_params(), 8)
+    assert L.depo_set_kernel_config(ctx64._h, 2, 8, 32, 1) == depo.E_INVALID
+    assert L.depo_set_kernel_config(ctx64._h, 1, 4, 16, 0) == depo.OK

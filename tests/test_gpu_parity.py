@@ -1,0 +1,281 @@
+"""GPU parity of the HIP path (through the C-ABI) against the FP64 oracle.
+
+FP64 runs are compared at round-off tolerances; the FP32 form is compared at
+the stated error bars: positions within 1e-5 R after 200 steps, force error
+relative to the sum of pair magnitudes within 1e-5, V_dep within its Monte
+Carlo standard error.  Particles whose discrete events differ between the two
+runs (deposition step) are excluded from position metrics and counted.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from synthetic import make_workload
+from synthetic.workloads import physical_params
+from tests.gpu_common import (coulomb_scale, force_error, near_wall_particles, oracle_from_snapshot,
+                              position_error, seeded_pair)
+from tests.oracle_helpers import uniform_field
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# ------------------------------------------------------------------------------------------ FP64 parity
+
+def test_fp64_plain_trajectory_matches_oracle():
+    w = make_workload("plain-1k", n=320, field_n=32)
+    f = w.field()
+    say("case: plain-1k n=320 fp64")
+    sim, ora = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 8)
+    g = sim.read()
+    scale = np.linalg.norm(ora.a, axis=1).max()
+    assert np.max(np.abs(g["a"] - ora.a)) <= 1e-10 * scale
+    assert np.max(np.abs(g["v"] - ora.v)) <= 1e-12
+    for chunk in (1, 4, 15):
+        sim.step(chunk)
+        ora.step(chunk)
+    g = sim.read()
+    assert np.array_equal(g["dep_step"], ora.dep_step)
+    al = ora.alive
+    assert np.max(position_error(g["x"][al], ora.x[al], ora.L, ora.R)) < 1e-12
+    assert np.max(np.abs(g["v"][al] - ora.v[al])) < 1e-9
+    assert np.max(np.abs(g["a"][al] - ora.a[al])) <= 1e-9 * scale
+
+
+def test_fp64_dense_cluster_contacts_and_neighbours():
+    """Tight cluster across the periodic seam next to the wall: contact, cohesion and Coulomb all active;
+    the cell-list neighbour counts equal brute force exactly."""
+    rng = np.random.default_rng(21)
+    n = 300
+    p = physical_params(180.0)
+    R, L = p["R"], p["L"]
+    d = rng.choice([5e-6, 10e-6, 20e-6], n)
+    x = np.stack([np.mod(rng.normal(0.0, 50e-6, n), L), R - 0.4e-3 + rng.normal(0, 50e-6, n),
+                  rng.normal(0, 50e-6, n)], 1)
+    q = rng.normal(0, 2e-15, n)
+    v0 = rng.normal(0, 0.05, (n, 3))
+    sp = np.array([[1.0, 2e-19, 300.0]])
+    f = make_workload("plain-1k", n=4, field_n=16).field()
+    off = np.array([0, n])
+    say("case: dense cluster n=300 fp64")
+    sim, ora = seeded_pair(p, f, x, d, q, off, sp, 8, v0=v0)
+    g = sim.read()
+    # brute-force neighbour counts (gap <= min(d_i, d_j)/4)
+    r = x[:, None, :] - x[None, :, :]
+    r[..., 0] -= L * np.round(r[..., 0] / L)
+    dist = np.linalg.norm(r, axis=-1)
+    gap = dist - 0.5 * (d[:, None] + d[None, :])
+    near = (gap <= 0.25 * np.minimum(d[:, None], d[None, :])) & (dist > 0)
+    assert np.array_equal(g["neighbours"], near.sum(axis=1))
+    assert near.sum() > 50 and (gap[near] < 0).sum() > 10
+    scale = np.linalg.norm(ora.a, axis=1)
+    assert np.max(np.linalg.norm(g["a"] - ora.a, axis=1) / (scale + 1e-30)) < 1e-9
+    sim.step(30)
+    ora.step(30)
+    g = sim.read()
+    assert np.array_equal(g["dep_step"], ora.dep_step)
+    al = ora.alive
+    assert np.max(position_error(g["x"][al], ora.x[al], L, R)) < 1e-10
+    assert np.max(np.linalg.norm(g["a"][al] - ora.a[al], axis=1) / (np.linalg.norm(ora.a[al], axis=1) + 1e-3)) < 1e-7
+
+
+def test_fp64_batched_samples_with_rebound():
+    w = make_workload("batched-256", n_samples=5, n_lo=60, n_hi=300, field_n=32)
+    f = w.field()
+    say("case: batched 5 samples fp64, N =", w.n_particles)
+    sim, ora = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 8)
+    sim.step(25)
+    ora.step(25)
+    g = sim.read()
+    assert np.array_equal(g["dep_step"], ora.dep_step)
+    al = ora.alive
+    assert np.max(position_error(g["x"][al], ora.x[al], ora.L, ora.R)) < 1e-12
+    scale = np.linalg.norm(ora.a[al], axis=1).max()
+    assert np.max(np.abs(g["a"][al] - ora.a[al])) < 1e-9 * scale
+
+
+def test_fp64_wall_removal_tally_and_rebound():
+    """Particles driven into the wall: removal step, tally and V_dep exactly as the oracle; with the
+    rebound law and weak cohesion some particles bounce back instead."""
+    rng = np.random.default_rng(3)
+    n = 400
+    for rebound in (False, True):
+        p = physical_params(180.0, rebound_osu=rebound, dt=2e-7)
+        d = rng.choice([5e-6, 10e-6], n)
+        x, er = near_wall_particles(rng, n, p, d, band=100e-6)
+        v0 = 1.5 * er + rng.normal(0, 0.1, (n, 3))
+        q = rng.normal(0, 1e-15, n)
+        sp = np.array([[1.0, 1e-22 if rebound else 1e-19, 300.0]])
+        f = make_workload("plain-1k", n=4, field_n=32).field()
+        say("case: wall tally fp64 rebound =", rebound)
+        sim, ora = seeded_pair(p, f, x, d, q, np.array([0, n]), sp, 8, v0=v0)
+        sim.step(60)
+        ora.step(60)
+        g = sim.read()
+        assert np.array_equal(g["dep_step"], ora.dep_step)
+        tg, to = sim.tally()[0], ora.tally()[0]
+        assert tg["n_dep"] == to["n_dep"] > 10
+        assert np.isclose(tg["m_dep"], to["m_dep"], rtol=1e-14)
+        assert np.isclose(tg["m_alive_dt"], to["m_alive_dt"], rtol=1e-13)
+        assert np.isclose(tg["v_dep"], to["v_dep"], rtol=1e-13)
+        assert np.isclose(tg["v_dep_plus"], to["v_dep_plus"], rtol=1e-13)
+        assert tg["n_alive"] == to["n_alive"]
+        al = ora.alive
+        assert np.max(position_error(g["x"][al], ora.x[al], ora.L, ora.R)) < 1e-11
+        if rebound:
+            # some particles reached the wall and survived
+            rho = np.hypot(x[:, 1], x[:, 2])
+            assert np.sum(al & (rho + 0.5 * d + 60 * 2e-7 * 1.0 > p["R"])) > 0
+
+
+def test_fp64_soft_tally():
+    rng = np.random.default_rng(4)
+    n = 256
+    p = physical_params(180.0, soft_tally=True, dt=1e-7)
+    d = np.full(n, 10e-6)
+    x, er = near_wall_particles(rng, n, p, d, band=20e-6)
+    v0 = 0.3 * er
+    sp = np.array([[0.05, 3e-19, 300.0]])
+    q = np.full(n, 8e-15)
+    f = make_workload("plain-1k", n=4, field_n=32).field()
+    say("case: soft tally fp64")
+    sim, ora = seeded_pair(p, f, x, d, q, np.array([0, n]), sp, 8, v0=v0)
+    sim.step(40)
+    ora.step(40)
+    tg, to = sim.tally()[0], ora.tally()[0]
+    assert to["j_soft"] > 0
+    assert np.isclose(tg["j_soft"], to["j_soft"], rtol=1e-11)
+    assert tg["n_dep"] == 0 and tg["n_alive"] == n
+
+
+# ------------------------------------------------------------------------------------------ FP32 form
+
+def test_fp32_plain_1k_200_steps_within_error_bars():
+    """The FP32 form on the full 1,024-particle workload over 200 steps: positions within 1e-5 R of
+    the FP64 oracle, same deposition events, V_dep within its Monte Carlo standard error."""
+    w = make_workload("plain-1k")
+    f = w.field()
+    say("case: plain-1k fp32 200 steps")
+    sim, ora = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4)
+    g0 = sim.read()
+    tg = np.arange(w.n_particles)
+    scale = coulomb_scale(ora, tg)
+    e0 = force_error(g0["a"], ora.a, scale)
+    say("seed force error max", e0.max())
+    assert e0.max() < 1e-5
+    sim.step(200)
+    ora.step(200)
+    g = sim.read()
+    both = (g["dep_step"] == 0) & ora.alive
+    n_event_diff = int(np.sum(g["dep_step"] != ora.dep_step))
+    err = position_error(g["x"][both], ora.x[both], ora.L, ora.R)
+    say("fp32 position error max/R", err.max(), "event differences", n_event_diff)
+    assert err.max() < 1e-5
+    assert n_event_diff <= 1
+    tgp, to = sim.tally()[0], ora.tally()[0]
+    se = max(to["v_dep_se"], tgp["v_dep_se"])
+    assert abs(tgp["v_dep"] - to["v_dep"]) <= se + 1e-30
+
+
+def test_fp32_single_65k_sampled_forces():
+    """Full 65,536-particle workload in the launch configuration the benchmark times: force error of
+    sampled targets against the oracle evaluated on the GPU's own snapshot, at seed and after 20 steps."""
+    w = make_workload("single-65k")
+    f = w.field()
+    say("case: single-65k fp32 sampled forces")
+    sim, _ = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4, oracle=False)
+    rng = np.random.default_rng(0)
+    targets = np.sort(rng.choice(w.n_particles, 96, replace=False))
+    for steps in (0, 20):
+        if steps:
+            sim.step(steps)
+            sim.eval_accel()
+        g = sim.read()
+        ora = oracle_from_snapshot(w.params, f, g, w.d, w.qbase, w.offsets, w.sample_params, g["dep_step"])
+        ok = targets[g["dep_step"][targets] == 0]
+        a_ora = ora.accelerations(ok)
+        e = force_error(g["a"][ok], a_ora, coulomb_scale(ora, ok))
+        say("steps", steps, "force error max", e.max(), "median", np.median(e))
+        assert e.max() < 1e-5
+
+
+def test_fp32_bitwise_deterministic_and_checkpoint_roundtrip():
+    w = make_workload("single-65k", n=8192, field_n=32)
+    f = w.field()
+    say("case: determinism / checkpoint fp32 n=8192")
+    runs = []
+    for _ in range(2):
+        sim, _ = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4, oracle=False)
+        sim.step(10)
+        runs.append(sim.read())
+    for k in ("x", "v", "a", "dep_step"):
+        assert np.array_equal(runs[0][k], runs[1][k]), k
+    blob = sim.state_download()
+    sim.step(7)
+    ref = sim.read()
+    tref = sim.tally()
+    sim.state_upload(blob)
+    sim.step(7)
+    got = sim.read()
+    for k in ("x", "v", "a", "dep_step"):
+        assert np.array_equal(ref[k], got[k]), k
+    assert sim.tally() == tref
+    from paper_2205_04979_amd.depo import DepoError, E_CORRUPT
+    bad = bytearray(blob)
+    bad[-5] ^= 0xFF
+    with pytest.raises(DepoError) as ei:
+        sim.state_upload(bytes(bad))
+    assert ei.value.status == E_CORRUPT
+    with pytest.raises(DepoError):
+        sim.state_upload(blob[:-8])
+
+
+def test_graph_replay_equals_direct_launch():
+    w = make_workload("single-65k", n=4096, field_n=32)
+    f = w.field()
+    say("case: graph replay vs direct launches fp32")
+    out = []
+    for graph in (True, False):
+        sim, _ = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4, oracle=False)
+        sim.set_kernel_config(1, 8, 32, use_graph=graph)
+        for _ in range(3):
+            sim.step(4)
+            out_k = sim.read()   # eager synchronisation between replays
+        out.append(out_k)
+    for k in ("x", "v", "a"):
+        assert np.array_equal(out[0][k], out[1][k]), k
+
+
+@pytest.mark.parametrize("cfg", [(1, 4, 32), (2, 8, 32), (4, 4, 32), (2, 16, 32)])
+def test_fp32_kernel_shapes_agree(cfg):
+    """Every compiled pair-kernel shape gives the same forces up to FP32 summation order."""
+    w = make_workload("single-65k", n=3000, field_n=32)
+    f = w.field()
+    say("case: pair-kernel shape", cfg)
+    sim, ora = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4)
+    sim.set_kernel_config(*cfg)
+    sim.eval_accel()
+    g = sim.read()
+    tg = np.arange(0, w.n_particles, 7)
+    e = force_error(g["a"][tg], ora.a[tg], coulomb_scale(ora, tg))
+    assert e.max() < 1e-5
+
+
+def test_nonfinite_is_reported():
+    """A non-finite input velocity is flagged on the device and reported by the next synchronising call."""
+    from paper_2205_04979_amd.depo import DepoError, E_NONFINITE
+    w = make_workload("plain-1k", n=64, field_n=16)
+    f = w.field()
+    v0 = np.zeros((64, 3))
+    v0[5, 0] = 1e30                  # finite on the host; overflows FP32 in the drag update
+    sim, _ = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4, v0=v0, oracle=False)
+    sim.step(1)
+    with pytest.raises(DepoError) as ei:
+        sim.tally()
+    assert ei.value.status == E_NONFINITE
