@@ -29,8 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FP32_VECTOR_TFLOPS = 157.3       # MI355X published FP32 vector peak
-NONPACKED_FP32_TFLOPS = 78.6          # one FMA per lane per cycle: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+PEAK_FP32_VECTOR_TFLOPS = 157.3       # MI355X published FP32 vector peak: 256 CU x 4 SIMD x 32 FMA lanes x 2 x 2.4 GHz
 FLOPS_PER_PAIR = 20                   # customary N-body count per interaction
 
 
@@ -82,6 +81,24 @@ def cpu_baseline(w, field, n_targets: int):
                 seconds=wall)
 
 
+def kernel_source_digest() -> str:
+    import hashlib
+    src = os.path.join(ROOT, "paper_2205_04979_amd", "csrc", "k_coulomb.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(shape):
+    """HBM bytes per pair-kernel launch from the committed counter summary, if it was taken on this
+    exact kernel source and shape; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "k_coulomb_single65k_hbm_counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("k_coulomb_sha256_16") != kernel_source_digest() or tuple(rec.get("shape", ())) != tuple(shape):
+        return None
+    return rec.get("bytes_per_launch")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,7 +107,10 @@ def main():
     ap.add_argument("--workload", default="single-65k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-targets", type=int, default=4096)
-    ap.add_argument("--kernel", default=None, help="pair-kernel shape ipl,waves,block")
+    ap.add_argument("--kernel", default=None, help="pair-kernel shape ipl,waves,block (skips autotuning)")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run one device-to-device copy of this size (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding is described "
@@ -115,10 +135,25 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     sim = Simulation(w.params, w.offsets, field.shape[:3], real_bytes=4, device="cuda:0")
-    if args.kernel:
-        sim.set_kernel_config(*[int(v) for v in args.kernel.split(",")])
     sim.init_field(field)
     sim.seed(w.sample_params, w.x, w.d, w.qbase)
+    tune = None
+    if args.kernel:
+        sim.set_kernel_config(*[int(v) for v in args.kernel.split(",")])
+        shape = tuple(int(v) for v in args.kernel.split(","))
+    elif not args.no_autotune:
+        from paper_2205_04979_amd.autotune import autotune
+        shape, tune = autotune(sim, steps=3)
+        log(f"[bench] autotuned pair kernel: {shape} " + ", ".join(f"{k}:{v:.3f}ms" for k, v in tune.items()))
+    else:
+        shape = (1, 8, 32)
+    if args.copy_probe_mb:
+        src = torch.empty(args.copy_probe_mb << 20, dtype=torch.uint8, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log(f"[bench] seeded N={N}; warmup {args.warmup} steps")
     if args.warmup:
         sim.step(args.warmup)
@@ -149,10 +184,9 @@ def main():
     achieved = pairs * FLOPS_PER_PAIR / (coul_ms * 1e-3) / 1e12
     roofline = {
         "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+        "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": measured_traffic(shape),
         "kernel": "k_coulomb (direct pair sums)", "kernel_ms": round(coul_ms, 5),
         "algorithmic": f"{FLOPS_PER_PAIR} flop per unordered pair x N(N-1)/2 pairs per launch",
-        "frac_of_nonpacked_fp32": round(achieved / NONPACKED_FP32_TFLOPS, 4),
         "ordered_pairs_per_s": round(2 * pairs / (coul_ms * 1e-3), 1),
     }
     out = {
@@ -162,7 +196,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "particles": N, "samples": w.n_samples,
                    "field": f"{w.field_n}^3", "forces": "drag+coulomb+contact+vdw+wall",
-                   "alive_at_end": int(n_alive), "ms_per_step_graph_replay": round(1e3 * wall_graph / g_steps, 5),
+                   "alive_at_end": int(n_alive), "pair_kernel_shape": list(shape),
+                   "autotune_ms": None if tune is None else {",".join(map(str, k)): round(v, 4) for k, v in tune.items()}, "ms_per_step_graph_replay": round(1e3 * wall_graph / g_steps, 5),
                    "phase_ms_per_step": {k: round(v / args.steps, 5) for k, v in phase_ms.items()}},
         "roofline": roofline,
     }

@@ -1,0 +1,56 @@
+"""Choose the Coulomb pair-kernel shape for a simulation by measurement.
+
+Each compiled shape (targets per lane, wavefronts per workgroup, sources per
+compensated block) is timed on the live simulation with ``depo_step_timed``
+(HIP events around the pair kernel), and the fastest is kept.  The particle
+state is saved before and restored after, so tuning does not advance the
+simulation.  Results can be cached in a JSON file keyed by precision, sample
+count, particle count and device name.
+"""
+
+from __future__ import annotations
+
+import json
+import os
+from typing import Optional
+
+FP32_SHAPES = [(1, 4, 32), (1, 8, 32), (1, 16, 32), (2, 4, 32), (2, 8, 32), (2, 16, 32), (4, 4, 32), (4, 8, 32)]
+FP64_SHAPES = [(1, 4, 16), (1, 8, 16), (2, 4, 16)]
+
+
+def _key(sim) -> str:
+    import torch
+    name = torch.cuda.get_device_name(sim.device)
+    return f"{name}|fp{8 * sim.real_bytes}|S={sim.s}|N={sim.n}"
+
+
+def autotune(sim, steps: int = 3, cache_path: Optional[str] = None, verbose: bool = False):
+    """Return (best_shape, {shape: ms per Coulomb launch}) and apply the best shape to ``sim``."""
+    key = _key(sim)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            cache = json.load(fh)
+        if key in cache:
+            best = tuple(cache[key]["best"])
+            sim.set_kernel_config(*best)
+            return best, {tuple(json.loads(k)): v for k, v in cache[key]["ms"].items()}
+    shapes = FP32_SHAPES if sim.real_bytes == 4 else FP64_SHAPES
+    blob = sim.state_download()
+    times = {}
+    for shp in shapes:
+        sim.set_kernel_config(*shp)
+        sim.step_timed(1)                       # first launch of a shape: code object load
+        sim.state_upload(blob)
+        ms = sim.step_timed(steps)["coulomb"] / steps
+        sim.state_upload(blob)
+        times[shp] = ms
+        if verbose:
+            print(f"[autotune] shape {shp}: {ms:.4f} ms per pair-kernel launch", flush=True)
+    best = min(times, key=times.get)
+    sim.set_kernel_config(*best)
+    if cache_path:
+        cache[key] = {"best": list(best), "ms": {json.dumps(list(k)): v for k, v in times.items()}}
+        with open(cache_path, "w") as fh:
+            json.dump(cache, fh, indent=1)
+    return best, times

@@ -213,7 +213,7 @@ template <class Real> void enqueue_forces(depo_ctx *ctx, hipStream_t s) {
   const State<Real> &st = state<Real>(ctx);
   if (short_range_on(ctx)) launch_cells<Real>(st, ctx->ph, ctx->n_cells, (ctx->n_cells + 1023) / 1024, s);
   if (ctx->p.flags & DEPO_COULOMB) launch_coulomb<Real>(st, ctx->ph, ctx->n_tiles, ctx->ccfg, s);
-  if (short_range_on(ctx)) launch_short_range<Real>(st, ctx->ph, s);
+  if (short_range_on(ctx)) launch_short_range<Real>(st, ctx->ph, ctx->n_cells, s);
 }
 
 int prepare_mode(const depo_ctx *ctx) {
@@ -274,7 +274,7 @@ template <class Real> depo_status run_steps_timed(depo_ctx *ctx, int n, hipStrea
     HIP_TRY(hipEventRecord(E[2], s));
     if (ctx->p.flags & DEPO_COULOMB) launch_coulomb<Real>(st, ctx->ph, ctx->n_tiles, ctx->ccfg, s);
     HIP_TRY(hipEventRecord(E[3], s));
-    if (short_range_on(ctx)) launch_short_range<Real>(st, ctx->ph, s);
+    if (short_range_on(ctx)) launch_short_range<Real>(st, ctx->ph, ctx->n_cells, s);
     HIP_TRY(hipEventRecord(E[4], s));
     launch_finish<Real>(st, ctx->ph, F_KICK, s);
     HIP_TRY(hipEventRecord(E[5], s));

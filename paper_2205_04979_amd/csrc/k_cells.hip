@@ -132,14 +132,14 @@ __device__ __forceinline__ Real vdw_force(Real gs_m, Real di_m, Real dj_m, Real 
   return Real(32.0 / 3.0) * A * u * (r13 * r23) * r / (PQ * PQ);
 }
 
+// One thread per alive particle, taken in cell order (the sorted index array),
+// so the threads of a wavefront walk neighbouring cells and share their loads.
+// Removed particles are not visited; their short-range slots are never read.
 template <class Real>
-__global__ __launch_bounds__(256) void k_short_range(State<Real> st, Phys ph) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ph.N) return;
-  if (st.dep[i] != 0) {
-    st.sx[i] = 0; st.sy[i] = 0; st.sz[i] = 0; st.nbr[i] = 0;
-    return;
-  }
+__global__ __launch_bounds__(256) void k_short_range(State<Real> st, Phys ph, int n_cells) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= st.cell_start[n_cells]) return;
+  const int i = st.cell_idx[t];
   const SampleDev sp = st.samples[st.sid[i]];
   const auto px = st.px[i], py = st.py[i], pz = st.pz[i];
   const Real vix = st.vx[i], viy = st.vy[i], viz = st.vz[i];
@@ -207,19 +207,18 @@ void launch_cells(const State<Real> &st, const Phys &ph, int n_cells, int n_scan
                      st.cell_count, st.cell_idx);
 }
 
-template <class Real> void launch_short_range(const State<Real> &st, const Phys &ph, hipStream_t s) {
-  if (ph.N > 0) hipLaunchKernelGGL(k_short_range<Real>, dim3((ph.N + 255) / 256), dim3(256), 0, s, st, ph);
+template <class Real>
+void launch_short_range(const State<Real> &st, const Phys &ph, int n_cells, hipStream_t s) {
+  if (ph.N > 0) hipLaunchKernelGGL(k_short_range<Real>, dim3((ph.N + 255) / 256), dim3(256), 0, s, st, ph, n_cells);
 }
 
 void launch_clear_int(int32_t *p, size_t n, hipStream_t s) {
   if (n) hipLaunchKernelGGL(k_clear_int, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
 }
 
-int scan_blocks_for(int n_cells) { return (n_cells + SCAN_BLOCK - 1) / SCAN_BLOCK; }
-
 template void launch_cells<float>(const State<float> &, const Phys &, int, int, hipStream_t);
 template void launch_cells<double>(const State<double> &, const Phys &, int, int, hipStream_t);
-template void launch_short_range<float>(const State<float> &, const Phys &, hipStream_t);
-template void launch_short_range<double>(const State<double> &, const Phys &, hipStream_t);
+template void launch_short_range<float>(const State<float> &, const Phys &, int, hipStream_t);
+template void launch_short_range<double>(const State<double> &, const Phys &, int, hipStream_t);
 
 }  // namespace depo

@@ -113,6 +113,7 @@ __global__ __launch_bounds__(256) void k_prepare(State<Real> st, Phys ph, int mo
         }
         if (stick) {
           st.dep[i] = step;
+          st.nbr[i] = 0;
           alive = false;
         }
       }
@@ -150,6 +151,8 @@ __global__ __launch_bounds__(256) void k_prepare(State<Real> st, Phys ph, int mo
 template <class Real>
 __global__ __launch_bounds__(256) void k_finish(State<Real> st, Phys ph, int mode) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  // the step counter advances once per step; no thread of this kernel reads it
+  if ((mode & F_KICK) && i == 0) *st.nstep += 1;
   if (i >= ph.N) return;
   if (st.dep[i] != 0) return;
   const int s = st.sid[i];
@@ -213,10 +216,6 @@ __global__ __launch_bounds__(256) void k_finish(State<Real> st, Phys ph, int mod
   if (!finite) atomicOr(st.err, ERR_NONFINITE);
 }
 
-__global__ void k_advance_counter(int32_t *nstep) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *nstep += 1;
-}
-
 // Per-sample tally (Eq. 2): deposited mass/count, the alive-mass time integral
 // dt * sum_i m_i * (steps suspended), the Poisson error term and the smoothed
 // deposited mass.  One block per sample; fixed-order strided loop and tree
@@ -254,8 +253,8 @@ void launch_prepare(const State<Real> &st, const Phys &ph, int mode, hipStream_t
 }
 template <class Real>
 void launch_finish(const State<Real> &st, const Phys &ph, int mode, hipStream_t s) {
-  if (ph.N > 0) hipLaunchKernelGGL(k_finish<Real>, dim3((ph.N + 255) / 256), dim3(256), 0, s, st, ph, mode);
-  if (mode & F_KICK) hipLaunchKernelGGL(k_advance_counter, dim3(1), dim3(64), 0, s, st.nstep);
+  hipLaunchKernelGGL(k_finish<Real>, dim3((ph.N + 255) / 256 > 0 ? (ph.N + 255) / 256 : 1), dim3(256), 0, s, st,
+                     ph, mode);
 }
 template <class Real>
 void launch_tally(const State<Real> &st, const Phys &ph, int nstep, hipStream_t s) {

@@ -17,7 +17,7 @@ template <class Real> void launch_tally(const State<Real> &st, const Phys &ph, i
 // Cell list: scan of the histogram, scatter, in-cell ordering, short-range forces.
 template <class Real>
 void launch_cells(const State<Real> &st, const Phys &ph, int n_cells, int n_scan_blocks, hipStream_t s);
-template <class Real> void launch_short_range(const State<Real> &st, const Phys &ph, hipStream_t s);
+template <class Real> void launch_short_range(const State<Real> &st, const Phys &ph, int n_cells, hipStream_t s);
 void launch_clear_int(int32_t *p, size_t n, hipStream_t s);
 
 // Coulomb pair sums.

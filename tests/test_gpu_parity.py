@@ -120,7 +120,9 @@ def test_fp64_wall_removal_tally_and_rebound():
         g = sim.read()
         assert np.array_equal(g["dep_step"], ora.dep_step)
         tg, to = sim.tally()[0], ora.tally()[0]
-        assert tg["n_dep"] == to["n_dep"] > 10
+        assert tg["n_dep"] == to["n_dep"]
+        if not rebound:
+            assert to["n_dep"] > 10
         assert np.isclose(tg["m_dep"], to["m_dep"], rtol=1e-14)
         assert np.isclose(tg["m_alive_dt"], to["m_alive_dt"], rtol=1e-13)
         assert np.isclose(tg["v_dep"], to["v_dep"], rtol=1e-13)
@@ -129,9 +131,10 @@ def test_fp64_wall_removal_tally_and_rebound():
         al = ora.alive
         assert np.max(position_error(g["x"][al], ora.x[al], ora.L, ora.R)) < 1e-11
         if rebound:
-            # some particles reached the wall and survived
-            rho = np.hypot(x[:, 1], x[:, 2])
-            assert np.sum(al & (rho + 0.5 * d + 60 * 2e-7 * 1.0 > p["R"])) > 0
+            # weak cohesion: impacts at ~1.5 m/s rebound (stick speed ~0.1 m/s), so particles come back inward
+            vr = np.sum(g["v"] * er, axis=1)
+            assert np.sum(vr < -1.0) > 10
+            assert np.allclose(vr, np.sum(ora.v * er, axis=1), rtol=0, atol=1e-9)
 
 
 def test_fp64_soft_tally():
@@ -272,10 +275,25 @@ def test_nonfinite_is_reported():
     from paper_2205_04979_amd.depo import DepoError, E_NONFINITE
     w = make_workload("plain-1k", n=64, field_n=16)
     f = w.field()
-    v0 = np.zeros((64, 3))
-    v0[5, 0] = 1e30                  # finite on the host; overflows FP32 in the drag update
-    sim, _ = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4, v0=v0, oracle=False)
+    q = w.qbase.copy()
+    q[5] = 1e30                      # finite on the host; its scaled charge overflows FP32 in the pair sums
+    sim, _ = seeded_pair(w.params, f, w.x, w.d, q, w.offsets, w.sample_params, 4, oracle=False)
     sim.step(1)
     with pytest.raises(DepoError) as ei:
         sim.tally()
     assert ei.value.status == E_NONFINITE
+
+
+def test_autotune_restores_state_and_picks_a_compiled_shape():
+    from paper_2205_04979_amd.autotune import FP32_SHAPES, autotune
+    w = make_workload("single-65k", n=4096, field_n=32)
+    f = w.field()
+    sim, _ = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4, oracle=False)
+    sim.step(3)
+    before = sim.read()
+    best, times = autotune(sim, steps=2)
+    after = sim.read()
+    assert best in FP32_SHAPES and set(times) == set(FP32_SHAPES)
+    for k in ("x", "v", "a", "dep_step"):
+        assert np.array_equal(before[k], after[k]), k
+    sim.step(2)            # still steps normally with the chosen shape
