@@ -99,6 +99,44 @@ def measured_traffic(shape):
     return rec.get("bytes_per_launch")
 
 
+def batched_run(steps: int) -> dict:
+    """The 256-sample Monte Carlo batch (uneven sample sizes, one launch per kernel family, graph replay)."""
+    import torch
+    from paper_2205_04979_amd.autotune import autotune
+    from paper_2205_04979_amd.depo import Simulation
+    from synthetic import make_workload
+    w = make_workload("batched-256")
+    field = w.field()
+    log(f"[bench] batched-256: S={w.n_samples} N={w.n_particles}")
+    sim = Simulation(w.params, w.offsets, field.shape[:3], real_bytes=4, device="cuda:0")
+    sim.init_field(field)
+    sim.seed(w.sample_params, w.x, w.d, w.qbase)
+    shape, _ = autotune(sim, steps=1)
+    sim.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ph = sim.step_timed(max(1, steps // 10))
+    n_tot = max(1, steps // 10)
+    ms = 1e3 * wall / steps
+    pairs = float(np.sum(np.diff(w.offsets).astype(np.float64) ** 2))
+    coul = ph["coulomb"] / n_tot
+    full = w.steps
+    res = {"workload": w.name, "samples": w.n_samples, "particles": w.n_particles, "steps_timed": steps,
+           "ms_per_step": round(ms, 4), "samples_per_s": round(w.n_samples / (full * ms * 1e-3), 4),
+           "sample_steps_per_s": round(w.n_samples * 1e3 / ms, 1),
+           "particle_steps_per_s": round(w.n_particles * 1e3 / ms, 1),
+           "coulomb_ms": round(coul, 4), "ordered_pairs_per_s": round(pairs / (coul * 1e-3), 1),
+           "pair_kernel_shape": list(shape),
+           "note": f"samples/s = {w.n_samples} samples / time of the full {full}-step run at the measured per-step time"}
+    log(f"[bench] batched: {res}")
+    del sim
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +147,8 @@ def main():
     ap.add_argument("--cpu-targets", type=int, default=4096)
     ap.add_argument("--kernel", default=None, help="pair-kernel shape ipl,waves,block (skips autotuning)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--secondary-steps", type=int, default=100,
+                    help="steps timed for the batched Monte Carlo workload (0 disables it)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run one device-to-device copy of this size (reference for HBM counters)")
     args = ap.parse_args()
@@ -201,6 +241,8 @@ def main():
                    "phase_ms_per_step": {k: round(v / args.steps, 5) for k, v in phase_ms.items()}},
         "roofline": roofline,
     }
+    if args.secondary_steps > 0 and args.workload == "single-65k":
+        out["batched"] = batched_run(args.secondary_steps)
     if cb is not None:
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline"]["value"] = round(cb["value"], 2)

@@ -190,12 +190,14 @@ depo_status depo_step(depo_ctx *ctx, int32_t n_steps, depo_stream stream);
 depo_status depo_step_timed(depo_ctx *ctx, int32_t n_steps, depo_stream stream, double *h_phase_ms);
 
 /* Choose the Coulomb pair-kernel shape (targets per lane, wavefronts per
- * workgroup, sources per compensated block) and whether depo_step replays a
- * captured HIP graph (use_graph != 0, the default) or launches kernels
- * directly.  DEPO_E_INVALID for a shape that is not compiled in.  Defaults:
- * (1, 8, 32) in FP32, (1, 4, 16) in FP64. */
+ * workgroup, sources per block, Kahan-compensated block accumulation on/off)
+ * and whether depo_step replays a captured HIP graph (use_graph != 0, the
+ * default) or launches kernels directly.  DEPO_E_INVALID for a shape that is
+ * not compiled in.  Defaults: (1, 8, 32, compensated) in FP32, (1, 4, 16,
+ * plain) in FP64; block 64 selects the variant that prefetches source records
+ * one group ahead. */
 depo_status depo_set_kernel_config(depo_ctx *ctx, int32_t targets_per_lane, int32_t waves, int32_t block,
-                                   int32_t use_graph);
+                                   int32_t compensated, int32_t use_graph);
 
 /* Recompute the non-drag acceleration of every alive particle at the
  * current positions and velocities (the force evaluation of a step without

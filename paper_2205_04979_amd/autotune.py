@@ -14,7 +14,8 @@ import json
 import os
 from typing import Optional
 
-FP32_SHAPES = [(1, 4, 32), (1, 8, 32), (1, 16, 32), (2, 4, 32), (2, 8, 32), (2, 16, 32), (4, 4, 32), (4, 8, 32)]
+FP32_SHAPES = [(1, 4, 32), (1, 8, 32), (1, 16, 32), (2, 4, 32), (2, 8, 32), (2, 16, 32), (4, 4, 32), (4, 8, 32),
+               (1, 4, 64), (1, 8, 64), (1, 16, 64), (2, 8, 64), (2, 16, 64)]
 FP64_SHAPES = [(1, 4, 16), (1, 8, 16), (2, 4, 16)]
 
 

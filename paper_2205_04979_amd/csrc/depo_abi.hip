@@ -75,7 +75,7 @@ struct depo_ctx {
   int n_tiles = 0;
   std::vector<SampleDev> samples;
   std::vector<depo_sample_params> sp;
-  CoulombConfig ccfg{1, 8, 32};
+  CoulombConfig ccfg{1, 8, 32, true};
   Phys ph{};
   State<float> sf{};
   State<double> sd{};
@@ -636,7 +636,7 @@ depo_status depo_create(const depo_params *p, depo_ctx **out) {
   if (!ok) return DEPO_E_INVALID;
   depo_ctx *ctx = new depo_ctx();
   ctx->p = *p;
-  if (ctx->fp64()) ctx->ccfg = CoulombConfig{1, 4, 16};
+  if (ctx->fp64()) ctx->ccfg = CoulombConfig{1, 4, 16, false};
   fill_phys(ctx);
   *out = ctx;
   return DEPO_OK;
@@ -762,11 +762,12 @@ depo_status depo_step_timed(depo_ctx *ctx, int32_t n_steps, depo_stream stream, 
 }
 
 depo_status depo_set_kernel_config(depo_ctx *ctx, int32_t targets_per_lane, int32_t waves, int32_t block,
-                                   int32_t use_graph) {
+                                   int32_t compensated, int32_t use_graph) {
   if (!ctx) return DEPO_E_INVALID;
-  CoulombConfig c{targets_per_lane, waves, block};
+  CoulombConfig c{targets_per_lane, waves, block, compensated != 0};
   if (!coulomb_config_supported(ctx->p.real_bytes, c))
-    return ctx->fail(DEPO_E_INVALID, "unsupported pair-kernel configuration (%d, %d, %d)", targets_per_lane, waves, block);
+    return ctx->fail(DEPO_E_INVALID, "unsupported pair-kernel configuration (%d, %d, %d, %d)", targets_per_lane, waves,
+                     block, compensated);
   ctx->ccfg = c;
   ctx->use_graph = use_graph != 0;
   ctx->drop_graph();

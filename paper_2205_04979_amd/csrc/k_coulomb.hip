@@ -30,7 +30,7 @@ namespace depo {
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
 
-template <class Real, int IPL, int WAVES, int BLK, bool KAHAN>
+template <class Real, int IPL, int WAVES, int BLK, bool KAHAN, bool PIPE>
 __global__ __launch_bounds__(64 * WAVES) void k_coulomb(const TileDev *__restrict__ tiles,
                                                         const JSrc<Real> *__restrict__ js,
                                                         const Real *__restrict__ jr, Real *__restrict__ ox,
@@ -61,35 +61,32 @@ __global__ __launch_bounds__(64 * WAVES) void k_coulomb(const TileDev *__restric
 #pragma unroll
   for (int k = 0; k < IPL; ++k) { hx[k] = hy[k] = hz[k] = cx[k] = cy[k] = cz[k] = Real(0); }
 
-  for (int j0 = jb; j0 < je; j0 += BLK) {
-    const int n = min(BLK, je - j0);
-    Real sx[IPL], sy[IPL], sz[IPL];
+  Real sx[IPL], sy[IPL], sz[IPL];
+  uint64_t nearmask = 0;
+
+  auto body = [&](const JSrc<Real> &s) {
+#pragma unroll
+    for (int k = 0; k < IPL; ++k) {
+      const Real dx = sdiff(xi[k], s.x);
+      const Real dy = yi[k] - s.y;
+      const Real dz = zi[k] - s.z;
+      const Real r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, Real(1))));
+      nearmask |= __builtin_amdgcn_ballot_w64(r2 < near2);
+      const Real inv = rsq(r2);
+      const Real wq = s.q * (inv * inv) * inv;
+      sx[k] = fma(wq, dx, sx[k]);
+      sy[k] = fma(wq, dy, sy[k]);
+      sz[k] = fma(wq, dz, sz[k]);
+    }
+  };
+  auto open_block = [&]() {
 #pragma unroll
     for (int k = 0; k < IPL; ++k) { sx[k] = sy[k] = sz[k] = Real(0); }
-    uint64_t nearmask = 0;
-
-    auto body = [&](const JSrc<Real> &s) {
-#pragma unroll
-      for (int k = 0; k < IPL; ++k) {
-        const Real dx = sdiff(xi[k], s.x);
-        const Real dy = yi[k] - s.y;
-        const Real dz = zi[k] - s.z;
-        const Real r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, Real(1))));
-        nearmask |= __builtin_amdgcn_ballot_w64(r2 < near2);
-        const Real inv = rsq(r2);
-        const Real wq = s.q * (inv * inv) * inv;
-        sx[k] = fma(wq, dx, sx[k]);
-        sy[k] = fma(wq, dy, sy[k]);
-        sz[k] = fma(wq, dz, sz[k]);
-      }
-    };
-    if (n == BLK) {
-#pragma unroll 8
-      for (int jj = 0; jj < BLK; ++jj) body(js[j0 + jj]);
-    } else {
-      for (int jj = 0; jj < n; ++jj) body(js[j0 + jj]);
-    }
-
+    nearmask = 0;
+  };
+  // close a block of n sources starting at j0: exact recompute if any pair was
+  // closer than the largest diameter, then compensated accumulation
+  auto close_block = [&](int j0, int n) {
     if (nearmask) {
       // exact overlap clamp for this block: r / (|r| max(|r|, d_ij)^2), zero at r = 0
 #pragma unroll
@@ -112,7 +109,6 @@ __global__ __launch_bounds__(64 * WAVES) void k_coulomb(const TileDev *__restric
         }
       }
     }
-
 #pragma unroll
     for (int k = 0; k < IPL; ++k) {
       if constexpr (KAHAN) {
@@ -124,6 +120,51 @@ __global__ __launch_bounds__(64 * WAVES) void k_coulomb(const TileDev *__restric
         hx[k] += sx[k]; hy[k] += sy[k]; hz[k] += sz[k];
       }
     }
+  };
+
+  int j0 = jb;
+  if constexpr (PIPE) {
+    // full blocks, source records prefetched one group of G ahead (across block
+    // boundaries) so the scalar-load latency overlaps the arithmetic
+    constexpr int G = 4;
+    JSrc<Real> cur[G];
+    if (j0 + BLK <= je) {
+#pragma unroll
+      for (int g = 0; g < G; ++g) cur[g] = js[j0 + g];
+    }
+    for (; j0 + BLK <= je; j0 += BLK) {
+      open_block();
+#pragma unroll 1
+      for (int jj = 0; jj < BLK; jj += G) {
+        const int jn = j0 + jj + G;
+        JSrc<Real> nxt[G];
+        const bool more = (jj + G < BLK) || (jn + BLK <= je);
+        if (more) {
+#pragma unroll
+          for (int g = 0; g < G; ++g) nxt[g] = js[jn + g];
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) body(cur[g]);
+        if (more) {
+#pragma unroll
+          for (int g = 0; g < G; ++g) cur[g] = nxt[g];
+        }
+      }
+      close_block(j0, BLK);
+    }
+  } else {
+    for (; j0 + BLK <= je; j0 += BLK) {
+      open_block();
+#pragma unroll 8
+      for (int jj = 0; jj < BLK; ++jj) body(js[j0 + jj]);
+      close_block(j0, BLK);
+    }
+  }
+  if (j0 < je) {   // ragged tail block
+    const int n = je - j0;
+    open_block();
+    for (int jj = 0; jj < n; ++jj) body(js[j0 + jj]);
+    close_block(j0, n);
   }
 
 #pragma unroll
@@ -145,15 +186,20 @@ __global__ __launch_bounds__(64 * WAVES) void k_coulomb(const TileDev *__restric
 
 int coulomb_tile_targets(const CoulombConfig &cfg) { return 64 * cfg.ipl; }
 
-#define DEPO_COULOMB_CASES(X)                                                                  \
-  X(float, 1, 4, 32, true) X(float, 1, 8, 32, true) X(float, 2, 4, 32, true)                    \
-  X(float, 2, 8, 32, true) X(float, 4, 4, 32, true) X(float, 4, 8, 32, true)                    \
-  X(float, 1, 16, 32, true) X(float, 2, 16, 32, true)                                           \
-  X(double, 1, 4, 16, false) X(double, 1, 8, 16, false) X(double, 2, 4, 16, false)
+// (type, targets per lane, waves, block, Kahan, prefetch); block 64 selects the prefetching variant
+#define DEPO_COULOMB_CASES(X)                                                                              \
+  X(float, 1, 4, 32, true, false) X(float, 1, 8, 32, true, false) X(float, 2, 4, 32, true, false)           \
+  X(float, 2, 8, 32, true, false) X(float, 4, 4, 32, true, false) X(float, 4, 8, 32, true, false)           \
+  X(float, 1, 16, 32, true, false) X(float, 2, 16, 32, true, false)                                         \
+  X(float, 1, 8, 64, true, true) X(float, 1, 16, 64, true, true) X(float, 2, 8, 64, true, true)             \
+  X(float, 2, 16, 64, true, true) X(float, 1, 4, 64, true, true)                                            \
+  X(float, 1, 16, 32, false, false)                                                                         \
+  X(double, 1, 4, 16, false, false) X(double, 1, 8, 16, false, false) X(double, 2, 4, 16, false, false)
 
 bool coulomb_config_supported(int real_bytes, const CoulombConfig &cfg) {
-#define X(R, I, W, B, K) \
-  if ((int)sizeof(R) == real_bytes && cfg.ipl == I && cfg.waves == W && cfg.block == B) return true;
+#define X(R, I, W, B, K, P) \
+  if ((int)sizeof(R) == real_bytes && cfg.ipl == I && cfg.waves == W && cfg.block == B && cfg.compensated == K) \
+    return true;
   DEPO_COULOMB_CASES(X)
 #undef X
   return false;
@@ -163,10 +209,10 @@ template <class Real>
 void launch_coulomb(const State<Real> &st, const Phys &ph, int n_tiles, const CoulombConfig &cfg, hipStream_t s) {
   if (n_tiles <= 0) return;
   const Real near2 = Real(ph.near2);
-#define X(R, I, W, B, K)                                                                                 \
+#define X(R, I, W, B, K, P)                                                                              \
   if constexpr (std::is_same<Real, R>::value) {                                                         \
-    if (cfg.ipl == I && cfg.waves == W && cfg.block == B) {                                             \
-      hipLaunchKernelGGL((k_coulomb<R, I, W, B, K>), dim3(n_tiles), dim3(64 * W), 0, s, st.tiles, st.js, \
+    if (cfg.ipl == I && cfg.waves == W && cfg.block == B && cfg.compensated == K) {                     \
+      hipLaunchKernelGGL((k_coulomb<R, I, W, B, K, P>), dim3(n_tiles), dim3(64 * W), 0, s, st.tiles, st.js, \
                          st.jr, st.cx, st.cy, st.cz, near2);                                             \
       return;                                                                                           \
     }                                                                                                   \

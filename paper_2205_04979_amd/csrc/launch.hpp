@@ -25,6 +25,7 @@ struct CoulombConfig {
   int ipl;     // targets per lane
   int waves;   // waves per workgroup (split the source range)
   int block;   // sources per compensated block
+  bool compensated;  // Kahan accumulation of the block sums (FP32); plain sums otherwise
 };
 template <class Real>
 void launch_coulomb(const State<Real> &st, const Phys &ph, int n_tiles, const CoulombConfig &cfg, hipStream_t s);

@@ -75,7 +75,7 @@ _SIGS = {
     "depo_set_sample_params": (C.c_int, [_P, C.POINTER(SampleParams), _P]),
     "depo_step": (C.c_int, [_P, C.c_int32, _P]),
     "depo_step_timed": (C.c_int, [_P, C.c_int32, _P, _DP]),
-    "depo_set_kernel_config": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "depo_set_kernel_config": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "depo_eval_accel": (C.c_int, [_P, _P]),
     "depo_read_particles": (C.c_int, [_P, _DP, _DP, _DP, _IP, _IP, _P]),
     "depo_tally_read": (C.c_int, [_P, C.POINTER(Tally), _P]),
@@ -242,9 +242,12 @@ class Simulation(Context):
         self.check(self._L.depo_set_sample_params(self._h, self._sp_array(sample_params), self._stream(stream)),
                    "depo_set_sample_params")
 
-    def set_kernel_config(self, targets_per_lane: int, waves: int, block: int, use_graph: bool = True):
-        self.check(self._L.depo_set_kernel_config(self._h, targets_per_lane, waves, block, int(use_graph)),
-                   "depo_set_kernel_config")
+    def set_kernel_config(self, targets_per_lane: int, waves: int, block: int, compensated: Optional[bool] = None,
+                          use_graph: bool = True):
+        if compensated is None:
+            compensated = self.real_bytes == 4
+        self.check(self._L.depo_set_kernel_config(self._h, targets_per_lane, waves, block, int(compensated),
+                                                  int(use_graph)), "depo_set_kernel_config")
 
     def step(self, n: int = 1, stream=None):
         self.check(self._L.depo_step(self._h, int(n), self._stream(stream)), "depo_step")

@@ -133,8 +133,11 @@ def test_calls_out_of_order_are_state_errors(depo):
 def test_kernel_config_validation(depo):
     ctx = depo.Context(physical_params(), 4)
     L = depo.lib()
-    assert L.depo_set_kernel_config(ctx._h, 3, 8, 32, 1) == depo.E_INVALID
-    assert L.depo_set_kernel_config(ctx._h, 2, 8, 32, 1) == depo.OK
+    assert L.depo_set_kernel_config(ctx._h, 3, 8, 32, 1, 1) == depo.E_INVALID
+    assert L.depo_set_kernel_config(ctx._h, 2, 8, 32, 1, 1) == depo.OK
+    assert L.depo_set_kernel_config(ctx._h, 2, 8, 32, 0, 1) == depo.E_INVALID     # plain sums: one shape only
+    assert L.depo_set_kernel_config(ctx._h, 1, 16, 32, 0, 1) == depo.OK
+    assert L.depo_set_kernel_config(ctx._h, 1, 16, 64, 1, 0) == depo.OK
     ctx64 = depo.Context(physical_params(), 8)
-    assert L.depo_set_kernel_config(ctx64._h, 2, 8, 32, 1) == depo.E_INVALID
-    assert L.depo_set_kernel_config(ctx64._h, 1, 4, 16, 0) == depo.OK
+    assert L.depo_set_kernel_config(ctx64._h, 2, 8, 32, 0, 1) == depo.E_INVALID
+    assert L.depo_set_kernel_config(ctx64._h, 1, 4, 16, 0, 0) == depo.OK

@@ -255,7 +255,7 @@ def test_graph_replay_equals_direct_launch():
         assert np.array_equal(out[0][k], out[1][k]), k
 
 
-@pytest.mark.parametrize("cfg", [(1, 4, 32), (2, 8, 32), (4, 4, 32), (2, 16, 32)])
+@pytest.mark.parametrize("cfg", [(1, 4, 32), (2, 8, 32), (4, 4, 32), (2, 16, 32), (1, 16, 64), (2, 8, 64)])
 def test_fp32_kernel_shapes_agree(cfg):
     """Every compiled pair-kernel shape gives the same forces up to FP32 summation order."""
     w = make_workload("single-65k", n=3000, field_n=32)
@@ -297,3 +297,51 @@ def test_autotune_restores_state_and_picks_a_compiled_shape():
     for k in ("x", "v", "a", "dep_step"):
         assert np.array_equal(before[k], after[k]), k
     sim.step(2)            # still steps normally with the chosen shape
+
+
+def test_fp32_batched_samples_sampled_forces():
+    """Many Monte Carlo samples of uneven size in one launch: per-sample force parity on sampled targets
+    (sources restricted to the target's own sample), at seed and after 10 steps."""
+    w = make_workload("batched-256", n_samples=24, n_lo=512, n_hi=6000, field_n=64)
+    f = w.field()
+    say("case: batched fp32, S =", w.n_samples, "N =", w.n_particles)
+    sim, _ = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4, oracle=False)
+    rng = np.random.default_rng(1)
+    targets = np.sort(np.concatenate([rng.choice(np.arange(w.offsets[s], w.offsets[s + 1]), 3, replace=False)
+                                      for s in range(w.n_samples)]))
+    for steps in (0, 10):
+        if steps:
+            sim.step(steps)
+            sim.eval_accel()
+        g = sim.read()
+        ora = oracle_from_snapshot(w.params, f, g, w.d, w.qbase, w.offsets, w.sample_params, g["dep_step"])
+        ok = targets[g["dep_step"][targets] == 0]
+        e = force_error(g["a"][ok], ora.accelerations(ok), coulomb_scale(ora, ok))
+        say("steps", steps, "force error max", e.max())
+        assert e.max() < 1e-5
+    t = sim.tally()
+    assert len(t) == w.n_samples and all(x["n_alive"] + x["n_dep"] == w.offsets[s + 1] - w.offsets[s]
+                                         for s, x in enumerate(t))
+
+
+def test_fp32_large_1m_force_error_compensated_vs_plain():
+    """The 2^20-particle workload: force error of 64 targets (index = 0 mod 16384) against the FP64 oracle
+    over all 1,048,576 sources, with compensated and with plain FP32 block sums."""
+    w = make_workload("large-1m")
+    f = w.field()
+    say("case: large-1m fp32 force error")
+    sim, _ = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4, oracle=False)
+    targets = np.arange(0, w.n_particles, 16384)
+    res = {}
+    for comp in (True, False):
+        sim.set_kernel_config(1, 16, 32, compensated=comp)
+        sim.eval_accel()
+        g = sim.read()
+        if comp:
+            ora = oracle_from_snapshot(w.params, f, g, w.d, w.qbase, w.offsets, w.sample_params, g["dep_step"])
+            a_ora = ora.accelerations(targets, chunk=4)
+            scale = coulomb_scale(ora, targets)
+        res[comp] = force_error(g["a"][targets], a_ora, scale)
+        say("compensated" if comp else "plain", "max", res[comp].max(), "median", np.median(res[comp]))
+    assert res[True].max() < 2e-6
+    assert np.median(res[True]) <= np.median(res[False])
