@@ -228,6 +228,29 @@ depo_status depo_state_download(depo_ctx *ctx, void *h_blob, size_t bytes, depo_
  * changed then).  Synchronises the stream. */
 depo_status depo_state_upload(depo_ctx *ctx, const void *h_blob, size_t bytes, depo_stream stream);
 
+/* Device bytes needed by depo_adjoint for n_steps and a checkpoint interval
+ * (1 <= ckpt_every <= n_steps): ceil(n_steps / ckpt_every) stored states, one
+ * segment of per-step states and the adjoint arrays.  Host only. */
+depo_status depo_adjoint_workspace_bytes(const depo_ctx *ctx, int32_t n_steps, int32_t ckpt_every, size_t *bytes);
+
+/* Gradient of J = sum_s w_s J_s, J_s = sum_{i in s} m_i (1 - exp(-l_i)) the
+ * smoothed deposited mass after n_steps, with respect to each sample's
+ * (charge_scale, hamaker, temperature) — the uncertain inputs of Sections 2.1
+ * and 4.4.  Hand-written reverse mode of the whole step (drag, gather, Coulomb
+ * pair sums, contact and cohesion, wall terms, smoothed tally) with
+ * checkpoints every ckpt_every steps and recomputation of each segment.
+ * Requires DEPO_SOFT_TALLY and a freshly seeded context (step 0): runs the
+ * n_steps forward (the context ends at step n_steps, exactly as after
+ * depo_step(n_steps)) and then the reverse sweep, including the dependence of
+ * the seeded acceleration on the parameters.  h_weights[S] = w_s;
+ * h_grad[S][3] receives dJ/d(charge_scale, hamaker, temperature); the
+ * temperature column is exactly 0 (it enters only the rebound law, which the
+ * smoothed tally turns off).  d_adj_work: caller-owned device memory of
+ * depo_adjoint_workspace_bytes() bytes, 256-byte aligned.  Synchronises the
+ * stream. */
+depo_status depo_adjoint(depo_ctx *ctx, int32_t n_steps, int32_t ckpt_every, const double *h_weights,
+                         double *h_grad, void *d_adj_work, size_t bytes, depo_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "adjoint.hpp"
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -75,6 +76,7 @@ struct depo_ctx {
   int n_tiles = 0;
   std::vector<SampleDev> samples;
   std::vector<depo_sample_params> sp;
+  double dmax_all = 0.0;
   CoulombConfig ccfg{1, 8, 32, true};
   Phys ph{};
   State<float> sf{};
@@ -344,6 +346,7 @@ depo_status build_samples(depo_ctx *ctx, const depo_sample_params *sp, const dou
   }
   if (cells > ctx->cell_cap) return ctx->fail(DEPO_E_CAPACITY, "cell grid exceeds reserved capacity");
   ctx->n_cells = (int)cells;
+  ctx->dmax_all = dmax_all;
   const double dq = dmax_all * ctx->ph.inv_ux;
   ctx->ph.near2 = dq * dq;
   return DEPO_OK;
@@ -604,6 +607,124 @@ template <class Real> depo_status do_upload(depo_ctx *ctx, const void *blob, siz
 
 }  // namespace
 
+// ---------------------------------------------------------------- adjoint
+
+template <class Real> struct AdjPlan {
+  std::vector<TapeEntry<Real>> ckpt, tape;
+  TapeEntry<Real> fin{};
+  AdjState<Real> ad{};
+};
+
+template <class Real>
+size_t carve_adjoint(const depo_ctx *ctx, char *base, int n_ckpt, int seg_len, AdjPlan<Real> &pl) {
+  using Pos = typename Prec<Real>::Pos;
+  const size_t N = (size_t)std::max<int64_t>(ctx->N, 1);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    char *p = base ? base + o : nullptr;
+    o = align_up(o + bytes);
+    return p;
+  };
+  auto entry = [&](bool ell) {
+    TapeEntry<Real> t{};
+    t.px = (Pos *)take(N * sizeof(Pos)); t.py = (Pos *)take(N * sizeof(Pos)); t.pz = (Pos *)take(N * sizeof(Pos));
+    Real **r[] = {&t.vx, &t.vy, &t.vz, &t.ax, &t.ay, &t.az, &t.ux, &t.uy, &t.uz, &t.cx, &t.cy, &t.cz};
+    for (Real **q : r) *q = (Real *)take(N * sizeof(Real));
+    t.ell = ell ? (double *)take(N * 8) : nullptr;
+    return t;
+  };
+  pl.ckpt.clear();
+  pl.tape.clear();
+  for (int k = 0; k < n_ckpt; ++k) pl.ckpt.push_back(entry(false));
+  for (int k = 0; k < seg_len; ++k) pl.tape.push_back(entry(false));   // tape[k] holds S_{k+1} of a segment
+  pl.fin = entry(true);
+  AdjState<Real> &a = pl.ad;
+  a.lam_ell = (Real *)take(N * sizeof(Real));
+  Real **arrs[] = {&a.xb[0], &a.xb[1], &a.xb[2], &a.vb[0], &a.vb[1], &a.vb[2], &a.ab[0], &a.ab[1], &a.ab[2],
+                   &a.ub[0], &a.ub[1], &a.ub[2], &a.xp[0], &a.xp[1], &a.xp[2], &a.vpb[0], &a.vpb[1], &a.vpb[2],
+                   &a.vp[0], &a.vp[1], &a.vp[2], &a.xc[0], &a.xc[1], &a.xc[2], &a.xs[0], &a.xs[1], &a.xs[2],
+                   &a.vs[0], &a.vs[1], &a.vs[2]};
+  for (Real **q : arrs) *q = (Real *)take(N * sizeof(Real));
+  a.gs = (double *)take(N * 8);
+  a.gA = (double *)take(N * 8);
+  a.rec = (JAdj<Real> *)take(N * sizeof(JAdj<Real>));
+  a.weights = (double *)take((size_t)ctx->S * 8);
+  a.out = (double *)take((size_t)ctx->S * 2 * 8);
+  return o;
+}
+
+template <class Real>
+depo_status do_adjoint(depo_ctx *ctx, int n, int ce, const double *hw, double *hg, void *dws, size_t bytes,
+                       hipStream_t s) {
+  AdjPlan<Real> pl;
+  const int K = (n + ce - 1) / ce;
+  const size_t need = carve_adjoint<Real>(ctx, nullptr, K, ce, pl);
+  if (bytes < need) return ctx->fail(DEPO_E_CAPACITY, "adjoint workspace needs %zu bytes", need);
+  carve_adjoint<Real>(ctx, (char *)dws, K, ce, pl);
+  const State<Real> &st = state<Real>(ctx);
+  const Phys &ph = ctx->ph;
+  const int N = (int)ctx->N;
+  const bool coul = (ctx->p.flags & DEPO_COULOMB) != 0, sr = short_range_on(ctx);
+  double wmax = 0.0;
+  for (int k = 0; k < ctx->S; ++k) wmax = std::max(wmax, std::fabs(hw[k]));
+  const double mmax = ph.mass_coef * ctx->dmax_all * ctx->dmax_all * ctx->dmax_all;
+  const double scale = (wmax > 0.0 && mmax > 0.0) ? 1.0 / (wmax * mmax) : 1.0;
+  HIP_TRY(hipMemcpyAsync(pl.ad.weights, hw, ctx->S * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  // forward run with checkpoints every ce steps
+  for (int k = 0; k < n; ++k) {
+    if (k % ce == 0) launch_tape_store<Real>(st, pl.ckpt[k / ce], N, false, s);
+    enqueue_step<Real>(ctx, s);
+  }
+  launch_tape_store<Real>(st, pl.fin, N, true, s);
+  launch_adj_init<Real>(st, ph, pl.ad, pl.ad.weights, scale, s);
+  auto rebuild_cells = [&]() {
+    if (sr) {
+      launch_prepare<Real>(st, ph, P_CELLS, s);
+      launch_cells<Real>(st, ph, ctx->n_cells, (ctx->n_cells + 1023) / 1024, s);
+    }
+  };
+  for (int seg = K - 1; seg >= 0; --seg) {
+    const int len = std::min(ce, n - seg * ce);
+    launch_tape_load<Real>(st, pl.ckpt[seg], N, false, s);
+    for (int k = 0; k < len; ++k) {
+      enqueue_step<Real>(ctx, s);
+      launch_tape_store<Real>(st, pl.tape[k], N, false, s);
+    }
+    for (int k = len - 1; k >= 0; --k) {
+      const TapeEntry<Real> &s0 = k == 0 ? pl.ckpt[seg] : pl.tape[k - 1];
+      const TapeEntry<Real> &s1 = pl.tape[k];
+      launch_tape_load<Real>(st, s1, N, false, s);
+      rebuild_cells();
+      launch_adj_post<Real>(st, ph, s0, s1, pl.ad, 0, s);
+      if (coul) launch_coulomb_vjp<Real>(st, ph, pl.ad, ctx->n_tiles, s);
+      if (sr) launch_short_range_vjp<Real>(st, ph, pl.ad, ctx->n_cells, 0, s);
+      launch_adj_pre<Real>(st, ph, s0, pl.ad, coul, sr, s);
+    }
+  }
+  // the seed's force evaluation a^0 = F(x^0, v^0; params)
+  launch_tape_load<Real>(st, pl.ckpt[0], N, false, s);
+  rebuild_cells();
+  launch_adj_post<Real>(st, ph, pl.ckpt[0], pl.ckpt[0], pl.ad, ADJ_SEED, s);
+  if (sr) launch_short_range_vjp<Real>(st, ph, pl.ad, ctx->n_cells, ADJ_SEED, s);
+  launch_adj_reduce<Real>(st, ph, pl.ad, pl.ad.out, s);
+  // back to the state after the forward run
+  launch_tape_load<Real>(st, pl.fin, N, true, s);
+  HIP_TRY(hipGetLastError());
+  std::vector<double> out((size_t)ctx->S * 2);
+  HIP_TRY(hipMemcpyAsync(out.data(), pl.ad.out, out.size() * 8, hipMemcpyDeviceToHost, s));
+  const int32_t ns = n;
+  HIP_TRY(hipMemcpyAsync(st.nstep, &ns, 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  ctx->nstep = n;
+  for (int k = 0; k < ctx->S; ++k) {
+    hg[3 * k + 0] = out[2 * k] / scale;
+    hg[3 * k + 1] = out[2 * k + 1] / scale;
+    hg[3 * k + 2] = 0.0;   // temperature enters only the rebound law, which the smoothed tally disables
+  }
+  return check_err<Real>(ctx, s);
+}
+
 #define DISPATCH(fn, ...) (ctx->fp64() ? fn<double>(__VA_ARGS__) : fn<float>(__VA_ARGS__))
 
 extern "C" {
@@ -833,4 +954,34 @@ depo_status depo_state_upload(depo_ctx *ctx, const void *h_blob, size_t bytes, d
   return DISPATCH(do_upload, ctx, h_blob, bytes, (hipStream_t)stream);
 }
 
+depo_status depo_adjoint_workspace_bytes(const depo_ctx *ctx, int32_t n_steps, int32_t ckpt_every, size_t *bytes) {
+  if (!ctx || !bytes) return DEPO_E_INVALID;
+  if (!ctx->has_layout) return DEPO_E_STATE;
+  if (n_steps < 1 || ckpt_every < 1 || ckpt_every > n_steps) return DEPO_E_INVALID;
+  const int K = (n_steps + ckpt_every - 1) / ckpt_every;
+  if (ctx->fp64()) {
+    AdjPlan<double> pl;
+    *bytes = carve_adjoint<double>(ctx, nullptr, K, ckpt_every, pl);
+  } else {
+    AdjPlan<float> pl;
+    *bytes = carve_adjoint<float>(ctx, nullptr, K, ckpt_every, pl);
+  }
+  return DEPO_OK;
+}
+
+depo_status depo_adjoint(depo_ctx *ctx, int32_t n_steps, int32_t ckpt_every, const double *h_weights,
+                         double *h_grad, void *d_adj_work, size_t bytes, depo_stream stream) {
+  if (!ctx) return DEPO_E_INVALID;
+  if (!ctx->seeded) return ctx->fail(DEPO_E_STATE, "seed first");
+  if (ctx->nstep != 0) return ctx->fail(DEPO_E_STATE, "the adjoint starts from the seeded state (step 0)");
+  if (!(ctx->p.flags & DEPO_SOFT_TALLY)) return ctx->fail(DEPO_E_INVALID, "the adjoint needs DEPO_SOFT_TALLY");
+  if (n_steps < 1 || ckpt_every < 1 || ckpt_every > n_steps) return ctx->fail(DEPO_E_INVALID, "need 1 <= ckpt_every <= n_steps");
+  if (!h_weights || !h_grad) return ctx->fail(DEPO_E_INVALID, "null weights or gradient array");
+  for (int k = 0; k < ctx->S; ++k)
+    if (!std::isfinite(h_weights[k])) return ctx->fail(DEPO_E_INVALID, "weight %d not finite", k);
+  if (!d_adj_work || ((uintptr_t)d_adj_work % kAlign) != 0) return ctx->fail(DEPO_E_INVALID, "adjoint workspace must be 256-byte aligned");
+  return DISPATCH(do_adjoint, ctx, n_steps, ckpt_every, h_weights, h_grad, d_adj_work, bytes, (hipStream_t)stream);
+}
+
 }  // extern "C"
+

@@ -82,6 +82,8 @@ _SIGS = {
     "depo_state_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
     "depo_state_download": (C.c_int, [_P, _P, C.c_size_t, _P]),
     "depo_state_upload": (C.c_int, [_P, _P, C.c_size_t, _P]),
+    "depo_adjoint_workspace_bytes": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    "depo_adjoint": (C.c_int, [_P, C.c_int32, C.c_int32, _DP, _DP, _P, C.c_size_t, _P]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -280,3 +282,53 @@ class Simulation(Context):
     def state_upload(self, blob: bytes, stream=None):
         buf = C.create_string_buffer(bytes(blob), len(blob))
         self.check(self._L.depo_state_upload(self._h, buf, len(blob), self._stream(stream)), "depo_state_upload")
+
+    def adjoint(self, n_steps: int, ckpt_every: int, weights=None, stream=None) -> np.ndarray:
+        """Run n_steps from the seeded state and return dJ/d(charge_scale, hamaker, temperature), shape (S, 3)."""
+        import torch
+        n = C.c_size_t()
+        self.check(self._L.depo_adjoint_workspace_bytes(self._h, int(n_steps), int(ckpt_every), C.byref(n)),
+                   "depo_adjoint_workspace_bytes")
+        w = np.ones(self.s) if weights is None else _f64(weights, (self.s,))
+        g = np.zeros((self.s, 3))
+        ws = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        aligned = (ws.data_ptr() + 255) // 256 * 256
+        self.check(self._L.depo_adjoint(self._h, int(n_steps), int(ckpt_every), _dptr(w), _dptr(g),
+                                        C.c_void_p(aligned), n.value, self._stream(stream)), "depo_adjoint")
+        del ws
+        return g
+
+
+def _autograd_function():
+    import torch
+
+    class DepositionFn(torch.autograd.Function):
+        """J_s = smoothed deposited mass of each sample after n_steps, differentiable in the per-sample
+        charge scale, Hamaker constant and temperature (hand-written adjoint in the library).
+
+        forward(charge_scale[S], hamaker[S], temperature[S], sim, seed, n_steps, ckpt_every) with
+        ``seed = dict(x=..., d=..., qbase=..., v=None)`` reseeds ``sim`` with these parameters."""
+
+        @staticmethod
+        def forward(ctx, charge_scale, hamaker, temperature, sim, seed, n_steps, ckpt_every):
+            sp = torch.stack([charge_scale, hamaker, temperature], 1).detach().cpu().double().numpy()
+            sim.seed(sp, seed["x"], seed["d"], seed["qbase"], v=seed.get("v"))
+            grad = sim.adjoint(n_steps, ckpt_every)
+            J = torch.tensor([t["j_soft"] for t in sim.tally()], dtype=torch.float64)
+            ctx.save_for_backward(torch.from_numpy(grad))
+            return J.to(charge_scale.device)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            (grad,) = ctx.saved_tensors
+            g = gJ.detach().cpu().double()[:, None] * grad
+            dev = gJ.device
+            return g[:, 0].to(dev), g[:, 1].to(dev), g[:, 2].to(dev), None, None, None, None
+
+    return DepositionFn
+
+
+def __getattr__(name):
+    if name == "DepositionFn":
+        return _autograd_function()
+    raise AttributeError(name)

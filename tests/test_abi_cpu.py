@@ -141,3 +141,23 @@ def test_kernel_config_validation(depo):
     ctx64 = depo.Context(physical_params(), 8)
     assert L.depo_set_kernel_config(ctx64._h, 2, 8, 32, 0, 1) == depo.E_INVALID
     assert L.depo_set_kernel_config(ctx64._h, 1, 4, 16, 0, 0) == depo.OK
+
+
+def test_adjoint_host_validation(depo):
+    L = depo.lib()
+    soft = physical_params(soft_tally=True)
+    ctx = depo.Context(soft, 4)
+    n = C.c_size_t()
+    assert L.depo_adjoint_workspace_bytes(ctx._h, 100, 10, C.byref(n)) == depo.E_STATE   # no layout yet
+    ctx.set_layout([0, 1000, 3000], 16, 16, 16)
+    assert L.depo_adjoint_workspace_bytes(ctx._h, 100, 101, C.byref(n)) == depo.E_INVALID
+    assert L.depo_adjoint_workspace_bytes(ctx._h, 0, 1, C.byref(n)) == depo.E_INVALID
+    sizes = []
+    for ce in (100, 10, 1):
+        assert L.depo_adjoint_workspace_bytes(ctx._h, 100, ce, C.byref(n)) == depo.OK
+        sizes.append(n.value)
+    # 1 checkpoint + 100 tape entries, 10 + 10, 100 + 1: per-entry cost is ~60 B per particle in FP32
+    assert sizes[1] < sizes[0] and sizes[1] < sizes[2]
+    w = (C.c_double * 2)(1.0, 1.0)
+    g = (C.c_double * 6)()
+    assert L.depo_adjoint(ctx._h, 10, 5, w, g, C.c_void_p(256), 1 << 30, None) == depo.E_STATE  # not seeded

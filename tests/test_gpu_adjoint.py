@@ -1,0 +1,204 @@
+"""Hand-written adjoint of the step (smoothed tally) against finite differences.
+
+References: central differences (relative step 1e-4 per parameter) of the FP64
+oracle's smoothed deposited mass, and of the library's own FP64 forward run.
+The workload places particles next to the wall so that the image charge
+(charge scale squared) and the wall and pair cohesion (Hamaker constant) move
+them measurably through the smoothed tally within the horizon.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.sim import OracleSim
+from synthetic import make_workload
+from synthetic.workloads import physical_params, q_max
+from tests.gpu_common import near_wall_particles
+
+pytestmark = pytest.mark.gpu
+
+H_REL = 1e-4
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def sensitive_case(n_per=120, S=2, seed=8):
+    rng = np.random.default_rng(seed)
+    p = physical_params(180.0, soft_tally=True, rebound_osu=True, dt=1e-6)
+    d = rng.choice([5e-6, 10e-6, 20e-6], n_per * S)
+    x, er = near_wall_particles(rng, n_per * S, p, d, band=6e-6)
+    # every 7th particle gets a partner at a surface gap of a fraction of a diameter (cohesion and
+    # Coulomb pairs; some overlap slightly, so contact forces act too)
+    a_idx = np.arange(0, n_per * S - 1, 7)
+    b_idx = a_idx + 1
+    gap = rng.uniform(-0.05, 0.2, a_idx.size) * np.minimum(d[a_idx], d[b_idx])
+    x[b_idx] = x[a_idx]
+    x[b_idx, 0] += 0.5 * (d[a_idx] + d[b_idx]) + gap
+    rr = np.hypot(x[:, 1], x[:, 2])
+    bad = rr + 0.5 * d >= p["R"] - 1e-7
+    x[bad, 1:] *= ((p["R"] - 0.5 * d[bad] - 2e-6) / rr[bad])[:, None]
+    v0 = 0.02 * er
+    q = q_max(d)
+    off = np.arange(S + 1) * n_per
+    sp = np.array([[0.08, 4e-19, 300.0], [0.05, 9e-19, 340.0]])[:S]
+    f = make_workload("plain-1k", n=4, field_n=32).field()
+    return p, f, x, d, q, off, sp, v0
+
+
+def oracle_J(p, f, x, d, q, off, sp, v0, n):
+    o = OracleSim(p, f, x, d, q, off, sp, v0=v0)
+    o.step(n)
+    return np.array([t["j_soft"] for t in o.tally()])
+
+
+def fd_oracle(p, f, x, d, q, off, sp, v0, n, h=None):
+    h = H_REL if h is None else h
+    g = np.zeros((sp.shape[0], 2))
+    for c in range(2):
+        hp, hm = sp.copy(), sp.copy()
+        hp[:, c] *= 1 + h
+        hm[:, c] *= 1 - h
+        g[:, c] = (oracle_J(p, f, x, d, q, off, hp, v0, n) - oracle_J(p, f, x, d, q, off, hm, v0, n)) / (
+            2 * h * sp[:, c])
+    return g
+
+
+def gpu_sim(p, f, off, real_bytes):
+    from paper_2205_04979_amd.depo import Simulation
+    sim = Simulation(p, off, f.shape[:3], real_bytes=real_bytes)
+    sim.init_field(f)
+    return sim
+
+
+def test_fp64_adjoint_matches_oracle_finite_differences():
+    """The cohesion cutoff (a jump of 0.27 A/d at gap d/4) makes J piecewise smooth; the adjoint
+    differentiates the smooth branch, so the seeded case is one where no cutoff crossing falls inside
+    the +-h interval: asserted here by the agreement of the h = 1e-4 and h = 1e-6 differences."""
+    p, f, x, d, q, off, sp, v0 = sensitive_case(seed=12)
+    n, ce = 30, 7
+    say("case: adjoint fp64 S=2 n=30 ckpt=7")
+    sim = gpu_sim(p, f, off, 8)
+    sim.seed(sp, x, d, q, v=v0)
+    g = sim.adjoint(n, ce)
+    fd = fd_oracle(p, f, x, d, q, off, sp, v0, n)
+    fd_fine = fd_oracle(p, f, x, d, q, off, sp, v0, n, h=1e-6)
+    assert np.max(np.abs(fd / fd_fine - 1)) < 2e-4
+    say("adjoint", g[:, :2].tolist(), "oracle FD", fd.tolist())
+    assert np.all(g[:, 2] == 0.0)
+    for s in range(sp.shape[0]):
+        for c in range(2):
+            assert abs(fd[s, c]) > 0
+            assert abs(g[s, c] - fd[s, c]) <= 1e-3 * abs(fd[s, c]), (s, c, g[s, c], fd[s, c])
+    # the context ends exactly where a plain forward run of n steps ends
+    after = sim.read()
+    ref = gpu_sim(p, f, off, 8)
+    ref.seed(sp, x, d, q, v=v0)
+    ref.step(n)
+    r = ref.read()
+    for k in ("x", "v", "a"):
+        assert np.array_equal(after[k], r[k]), k
+    assert sim.tally() == ref.tally()
+
+
+def test_fp64_adjoint_matches_gpu_finite_differences_and_is_checkpoint_invariant():
+    p, f, x, d, q, off, sp, v0 = sensitive_case(seed=9)
+    n = 24
+    say("case: adjoint fp64 vs gpu FD, checkpoint invariance")
+    sim = gpu_sim(p, f, off, 8)
+    grads = []
+    for ce in (1, 5, 24):
+        sim.seed(sp, x, d, q, v=v0)
+        grads.append(sim.adjoint(n, ce))
+    assert np.array_equal(grads[0], grads[1]) and np.array_equal(grads[0], grads[2])
+
+    def J(spp):
+        sim.seed(spp, x, d, q, v=v0)
+        sim.step(n)
+        return np.array([t["j_soft"] for t in sim.tally()])
+
+    for c in range(2):
+        fds = []
+        for h in (H_REL, 1e-6):
+            hp, hm = sp.copy(), sp.copy()
+            hp[:, c] *= 1 + h
+            hm[:, c] *= 1 - h
+            fds.append((J(hp) - J(hm)) / (2 * h * sp[:, c]))
+        assert np.allclose(fds[0], fds[1], rtol=2e-4, atol=0)      # smooth over the +-h interval
+        assert np.allclose(grads[0][:, c], fds[0], rtol=1e-3, atol=0), (c, grads[0][:, c], fds[0])
+
+
+def test_fp32_adjoint_close_to_fp64_adjoint():
+    p, f, x, d, q, off, sp, v0 = sensitive_case(seed=10)
+    n, ce = 20, 10
+    say("case: adjoint fp32 vs fp64")
+    g = {}
+    for rb in (8, 4):
+        sim = gpu_sim(p, f, off, rb)
+        sim.seed(sp, x, d, q, v=v0)
+        g[rb] = sim.adjoint(n, ce)
+    say("fp64", g[8][:, :2].tolist(), "fp32", g[4][:, :2].tolist())
+    assert np.allclose(g[4][:, :2], g[8][:, :2], rtol=2e-3, atol=0)
+
+
+def test_autograd_function_backward():
+    import torch
+    from paper_2205_04979_amd.depo import DepositionFn
+    p, f, x, d, q, off, sp, v0 = sensitive_case(seed=11)
+    n, ce = 12, 4
+    sim = gpu_sim(p, f, off, 8)
+    cs = torch.tensor(sp[:, 0], dtype=torch.float64, requires_grad=True)
+    A = torch.tensor(sp[:, 1], dtype=torch.float64, requires_grad=True)
+    T = torch.tensor(sp[:, 2], dtype=torch.float64, requires_grad=True)
+    J = DepositionFn.apply(cs, A, T, sim, dict(x=x, d=d, qbase=q, v=v0), n, ce)
+    w = torch.tensor([2.0, -0.5], dtype=torch.float64)
+    (J * w).sum().backward()
+    sim.seed(sp, x, d, q, v=v0)
+    g = sim.adjoint(n, ce)
+    assert np.allclose(cs.grad.numpy(), w.numpy() * g[:, 0], rtol=1e-12)
+    assert np.allclose(A.grad.numpy(), w.numpy() * g[:, 1], rtol=1e-12)
+    assert np.all(T.grad.numpy() == 0.0)
+
+
+FORCE_SETS = {
+    "drag+image": dict(drag=True, coulomb=False, collide=False, vdw=False, wall_image=True, wall_vdw=False),
+    "coulomb": dict(drag=False, coulomb=True, collide=False, vdw=False, wall_image=False, wall_vdw=False),
+    "contact+pair-vdw": dict(drag=False, coulomb=False, collide=True, vdw=True, wall_image=False, wall_vdw=False),
+    "drag+wall-vdw": dict(drag=True, coulomb=False, collide=False, vdw=False, wall_image=False, wall_vdw=True),
+}
+
+
+@pytest.mark.parametrize("name", list(FORCE_SETS))
+def test_fp64_adjoint_per_force_family(name):
+    """Each force family alone: adjoint against central differences of the library's FP64 forward run
+    (itself at round-off parity with the oracle); parameters a family does not use have gradient 0."""
+    p, f, x, d, q, off, sp, v0 = sensitive_case(seed=17)
+    p.update(FORCE_SETS[name])
+    n, ce = 16, 5
+    say("case: adjoint family", name)
+    sim = gpu_sim(p, f, off, 8)
+    sim.seed(sp, x, d, q, v=v0)
+    g = sim.adjoint(n, ce)
+
+    def J(spp):
+        sim.seed(spp, x, d, q, v=v0)
+        sim.step(n)
+        return np.array([t["j_soft"] for t in sim.tally()])
+
+    for c in range(2):
+        fds = []
+        for h in (H_REL, 1e-6):
+            hp, hm = sp.copy(), sp.copy()
+            hp[:, c] *= 1 + h
+            hm[:, c] *= 1 - h
+            fds.append((J(hp) - J(hm)) / (2 * h * sp[:, c]))
+        say(name, "param", c, "adjoint", g[:, c].tolist(), "fd", fds[0].tolist(), fds[1].tolist())
+        if np.all(fds[1] == 0.0):
+            assert np.all(g[:, c] == 0.0)
+            continue
+        assert np.allclose(fds[0], fds[1], rtol=2e-4, atol=0)
+        assert np.allclose(g[:, c], fds[0], rtol=1e-3, atol=0), (name, c, g[:, c], fds[0])
