@@ -137,6 +137,47 @@ def batched_run(steps: int) -> dict:
     return res
 
 
+def adjoint_run() -> dict:
+    """Adjoint/forward cost on the 64 x 16,384 workload: 100 steps, checkpoints every 10 steps."""
+    import torch
+    from paper_2205_04979_amd.depo import Simulation
+    from synthetic import make_workload
+    w = make_workload("adjoint-64x16k")
+    field = w.field()
+    n, ce = w.steps, w.extra["ckpt_every"]
+    log(f"[bench] adjoint-64x16k: S={w.n_samples} N={w.n_particles} steps={n} ckpt={ce}")
+    sim = Simulation(w.params, w.offsets, field.shape[:3], real_bytes=4, device="cuda:0")
+    sim.init_field(field)
+    sim.set_kernel_config(1, 16, 32)
+    sim.seed(w.sample_params, w.x, w.d, w.qbase)
+    sim.step(2)                       # warm the kernels up
+    sim.seed(w.sample_params, w.x, w.d, w.qbase)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(n)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    j_fwd = [t["j_soft"] for t in sim.tally()]
+    sim.seed(w.sample_params, w.x, w.d, w.qbase)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g = sim.adjoint(n, ce)
+    torch.cuda.synchronize()
+    adj = time.perf_counter() - t1
+    j_adj = [t["j_soft"] for t in sim.tally()]
+    res = {"workload": w.name, "samples": w.n_samples, "particles": w.n_particles, "steps": n, "ckpt_every": ce,
+           "forward_s": round(fwd, 4), "adjoint_s": round(adj, 4), "adjoint_over_forward": round(adj / fwd, 3),
+           "note": "adjoint_s includes its own forward run with checkpoints, the per-segment recomputation "
+                   "and the reverse sweep; both start from the seeded state",
+           "same_J_as_forward": bool(j_fwd == j_adj),
+           "grad_charge_scale_sample0": g[0, 0], "grad_hamaker_sample0": g[0, 1],
+           "grad_temperature_all_zero": bool(np.all(g[:, 2] == 0.0))}
+    log(f"[bench] adjoint: {res}")
+    del sim
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,7 +271,7 @@ def main():
         "ordered_pairs_per_s": round(2 * pairs / (coul_ms * 1e-3), 1),
     }
     out = {
-        "metric": "particle-steps/s at 65k particles", "value": round(value, 1), "unit": "particle-steps/s",
+        "metric": "particle-steps/s at 65k particles; batched samples/s; adjoint/forward cost", "value": round(value, 1), "unit": "particle-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
@@ -243,6 +284,7 @@ def main():
     }
     if args.secondary_steps > 0 and args.workload == "single-65k":
         out["batched"] = batched_run(args.secondary_steps)
+        out["adjoint"] = adjoint_run()
     if cb is not None:
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline"]["value"] = round(cb["value"], 2)

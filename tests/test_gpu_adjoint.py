@@ -123,12 +123,12 @@ def test_fp64_adjoint_matches_gpu_finite_differences_and_is_checkpoint_invariant
 
     for c in range(2):
         fds = []
-        for h in (H_REL, 1e-6):
+        for h in (H_REL, 3 * H_REL):
             hp, hm = sp.copy(), sp.copy()
             hp[:, c] *= 1 + h
             hm[:, c] *= 1 - h
             fds.append((J(hp) - J(hm)) / (2 * h * sp[:, c]))
-        assert np.allclose(fds[0], fds[1], rtol=2e-4, atol=0)      # smooth over the +-h interval
+        assert np.allclose(fds[0], fds[1], rtol=2e-4, atol=0)      # smooth over the +-3h interval
         assert np.allclose(grads[0][:, c], fds[0], rtol=1e-3, atol=0), (c, grads[0][:, c], fds[0])
 
 
@@ -175,7 +175,9 @@ FORCE_SETS = {
 @pytest.mark.parametrize("name", list(FORCE_SETS))
 def test_fp64_adjoint_per_force_family(name):
     """Each force family alone: adjoint against central differences of the library's FP64 forward run
-    (itself at round-off parity with the oracle); parameters a family does not use have gradient 0."""
+    (itself at round-off parity with the oracle); parameters a family does not use have gradient 0.
+    Smoothness over the interval is checked with a second, coarser step (3h): a finer step would move
+    particles by only a few 64-bit fixed-point position quanta and measure rounding instead."""
     p, f, x, d, q, off, sp, v0 = sensitive_case(seed=17)
     p.update(FORCE_SETS[name])
     n, ce = 16, 5
@@ -191,13 +193,13 @@ def test_fp64_adjoint_per_force_family(name):
 
     for c in range(2):
         fds = []
-        for h in (H_REL, 1e-6):
+        for h in (H_REL, 3 * H_REL):
             hp, hm = sp.copy(), sp.copy()
             hp[:, c] *= 1 + h
             hm[:, c] *= 1 - h
             fds.append((J(hp) - J(hm)) / (2 * h * sp[:, c]))
         say(name, "param", c, "adjoint", g[:, c].tolist(), "fd", fds[0].tolist(), fds[1].tolist())
-        if np.all(fds[1] == 0.0):
+        if np.all(fds[0] == 0.0) and np.all(fds[1] == 0.0):
             assert np.all(g[:, c] == 0.0)
             continue
         assert np.allclose(fds[0], fds[1], rtol=2e-4, atol=0)
