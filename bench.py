@@ -188,6 +188,8 @@ def main():
     ap.add_argument("--cpu-targets", type=int, default=4096)
     ap.add_argument("--kernel", default=None, help="pair-kernel shape ipl,waves,block (skips autotuning)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--legs", default="single,batched,adjoint",
+                    help="which measurements to run: single (the headline), batched, adjoint")
     ap.add_argument("--secondary-steps", type=int, default=100,
                     help="steps timed for the batched Monte Carlo workload (0 disables it)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -197,6 +199,19 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding is described "
                                    "in DESIGN.md and not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
+
+    legs = set(args.legs.split(","))
+    if "single" not in legs:
+        # profiling runs of the secondary legs only (no headline line)
+        import torch
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        out = {}
+        if "batched" in legs:
+            out["batched"] = batched_run(args.secondary_steps)
+        if "adjoint" in legs:
+            out["adjoint"] = adjoint_run()
+        print(json.dumps(out), flush=True)
+        return
 
     from synthetic import make_workload
 
@@ -283,8 +298,10 @@ def main():
         "roofline": roofline,
     }
     if args.secondary_steps > 0 and args.workload == "single-65k":
-        out["batched"] = batched_run(args.secondary_steps)
-        out["adjoint"] = adjoint_run()
+        if "batched" in legs:
+            out["batched"] = batched_run(args.secondary_steps)
+        if "adjoint" in legs:
+            out["adjoint"] = adjoint_run()
     if cb is not None:
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline"]["value"] = round(cb["value"], 2)
