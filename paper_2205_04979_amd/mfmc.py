@@ -33,6 +33,9 @@ def allocate(sigma: Sequence[float], rho: Sequence[float], w: Sequence[float], b
     r1 = np.asarray(rho, dtype=np.float64)
     ww = np.asarray(w, dtype=np.float64)
     k = s.shape[0]
+    if not (np.all(np.isfinite(s)) and np.all(s > 0) and np.all(np.isfinite(r1)) and np.all(np.abs(r1) <= 1)
+            and abs(r1[1]) < 1 and np.all(ww > 0)):
+        raise ValueError("allocation needs sigma > 0, |rho| <= 1 with |rho_12| < 1 and positive costs")
     alpha = np.ones(k)
     alpha[1:] = r1[1:] * s[0] / s[1:]
     nxt = np.zeros(k)

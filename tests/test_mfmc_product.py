@@ -80,25 +80,62 @@ def test_gpu_hf_batch_equals_single_sample_runs_and_oracle():
     assert batch[0] != batch[2]
 
 
+def _oracle_model(p, f, x, d, v0, steps):
+    """The same evaluator as HighFidelityGPU, one FP64 oracle run per input point."""
+    from oracle.sim import OracleSim
+    from synthetic.workloads import q_max
+    n = x.shape[0]
+
+    def run(pts):
+        out = np.empty(pts.shape[0])
+        for k in range(pts.shape[0]):
+            sp = np.array([[pts[k, 0], pts[k, 1] * 1e-18, pts[k, 2]]])
+            o = OracleSim(p, f, x, d, q_max(d), np.array([0, n]), sp, v0=v0)
+            o.step(steps)
+            out[k] = o.tally()[0]["v_dep_plus"]
+        return out
+    return run
+
+
 @pytest.mark.gpu
-def test_gpu_mfmc_pipeline_end_to_end():
-    """MFMC mean and Sobol' indices with the GPU HF model and a cheaper GPU model (fewer particles,
-    shorter run) as the low-fidelity surrogate; counts follow the allocation, outputs are finite."""
+def test_gpu_mfmc_pipeline_matches_oracle_pipeline():
+    """MFMC mean, variance and Sobol' indices with the GPU model (FP64) as HF and a cheaper GPU model
+    (fewer particles, shorter run) as LF, against the same pipeline evaluated with the oracle as both
+    models on the same seeded inputs."""
     from synthetic import make_workload
     from synthetic.workloads import physical_params
     from tests.gpu_common import near_wall_particles
     rng = np.random.default_rng(3)
-    p = physical_params(180.0, dt=2e-7)
+    n = 200
+    p = physical_params(180.0, rebound_osu=True, dt=2e-7)
     f = make_workload("plain-1k", n=4, field_n=32).field()
-    d = rng.choice([5e-6, 10e-6], 400)
-    x, _ = near_wall_particles(rng, 400, p, d, band=60e-6)
-    hf = pmf.HighFidelityGPU(p, f, x, d, steps=60)
-    lf = pmf.HighFidelityGPU(p, f, x[:100], d[:100], steps=30)
-    sample = lambda r, m: np.stack([r.uniform(0, 0.1, m), r.uniform(0, 1, m), r.uniform(280, 360, m)], 1)  # noqa
+    d = rng.choice([5e-6, 10e-6], n)
+    x, er = near_wall_particles(rng, n, p, d, band=100e-6)
+    v0 = 1.5 * er + rng.normal(0, 0.1, (n, 3))
+    hf = pmf.HighFidelityGPU(p, f, x, d, steps=60, real_bytes=8, v=v0)
+    lf = pmf.HighFidelityGPU(p, f, x[:50], d[:50], steps=30, real_bytes=8, v=v0[:50])
+    sample = lambda r, m: np.stack([r.uniform(0, 0.1, m), 10 ** r.uniform(-5, 0, m),   # noqa: E731
+                                    r.uniform(280, 360, m)], 1)
     pilot = sample(np.random.default_rng(4), 16)
+    print("case: MFMC pipeline, pilot", flush=True)
     yh, yl = hf(pilot), lf(pilot)
-    sigma = (max(yh.std(), 1e-30), max(yl.std(), 1e-30))
-    rho = (1.0, float(np.clip(np.corrcoef(yh, yl)[0, 1], 0.05, 0.999)))
-    res = pmf.mfmc_sobol([hf, lf], sigma, rho, (1.0, 0.125), 60.0, sample, 3, np.random.default_rng(5))
-    assert res.counts[1] >= res.counts[0] >= 2
-    assert np.isfinite(res.mean) and np.all(np.isfinite(res.main))
+    assert yh.std() > 0 and yl.std() > 0
+    sigma, rho = (yh.std(ddof=1), yl.std(ddof=1)), (1.0, float(np.corrcoef(yh, yl)[0, 1]))
+    args = (sigma, rho, (1.0, 0.1), 40.0, sample, 3)
+    print("case: MFMC pipeline, GPU models", sigma, rho, flush=True)
+    res = pmf.mfmc_sobol([hf, lf], *args, rng=np.random.default_rng(5))
+    assert res.counts[1] > res.counts[0] >= 2
+    print("case: MFMC pipeline, oracle models", res.counts.tolist(), flush=True)
+    ref = pmf.mfmc_sobol([_oracle_model(p, f, x, d, v0, 60), _oracle_model(p, f, x[:50], d[:50], v0[:50], 30)],
+                         *args, rng=np.random.default_rng(5))
+    assert np.array_equal(res.counts, ref.counts)
+    for a, b in ((res.mean, ref.mean), (res.variance, ref.variance)):
+        assert np.isclose(a, b, rtol=1e-11, atol=0), (a, b)
+    assert np.allclose(res.main, ref.main, rtol=1e-9, atol=1e-12)
+    assert np.allclose(res.total, ref.total, rtol=1e-9, atol=1e-12)
+
+
+def test_allocation_rejects_degenerate_statistics():
+    for sigma, rho in (((1.0, 0.0), (1.0, 0.5)), ((1.0, 1.0), (1.0, float("nan"))), ((1.0, 1.0), (1.0, 1.0))):
+        with pytest.raises(ValueError):
+            pmf.allocate(sigma, rho, (1.0, 0.1), 10.0)
