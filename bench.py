@@ -179,6 +179,46 @@ def adjoint_run() -> dict:
     return res
 
 
+def rebound_run() -> dict:
+    """The temperature study of Section 4.4: 64 samples x 16,384 particles, theta ~ U[0, 1], rebound law,
+    the whole 1,000-step run timed; reports throughput and the capture efficiency (Eq. CE) per sample."""
+    import torch
+    from paper_2205_04979_amd.depo import Simulation
+    from synthetic import make_workload
+    w = make_workload("rebound-theta-64")
+    field = w.field()
+    log(f"[bench] rebound-theta-64: S={w.n_samples} N={w.n_particles} steps={w.steps}")
+    sim = Simulation(w.params, w.offsets, field.shape[:3], real_bytes=4, device="cuda:0")
+    sim.init_field(field)
+    sim.set_kernel_config(1, 16, 32)
+    sim.seed(w.sample_params, w.x, w.d, w.qbase)
+    sim.step(2)                       # warm the kernels up
+    sim.seed(w.sample_params, w.x, w.d, w.qbase)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(w.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tal = sim.tally()
+    ce = np.array([t["ce"] for t in tal])
+    theta = 0.225 * (w.sample_params[:, 2] - 1000.0) / 200.0
+    hot = theta >= 0.9
+    res = {"workload": w.name, "samples": w.n_samples, "particles": w.n_particles, "steps": w.steps,
+           "dt": w.params["dt"], "wall_s": round(wall, 4), "ms_per_step": round(1e3 * wall / w.steps, 4),
+           "samples_per_s": round(w.n_samples / wall, 4),
+           "particle_steps_per_s": round(w.n_particles * w.steps / wall, 1),
+           "deposited": int(sum(t["n_dep"] for t in tal)),
+           "ce_mean": float(ce.mean()), "ce_std": float(ce.std(ddof=1)),
+           "ce_mean_theta_below_0.9": float(ce[~hot].mean()) if np.any(~hot) else None,
+           "ce_mean_theta_above_0.9": float(ce[hot].mean()) if np.any(hot) else None,
+           "ce_corr_with_theta": float(np.corrcoef(theta, ce)[0, 1]),
+           "ce_corr_with_zeta": float(np.corrcoef(w.extra["zeta"], ce)[0, 1])}
+    log(f"[bench] rebound: {res}")
+    del sim
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,8 +229,8 @@ def main():
     ap.add_argument("--cpu-targets", type=int, default=4096)
     ap.add_argument("--kernel", default=None, help="pair-kernel shape ipl,waves,block (skips autotuning)")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--legs", default="single,batched,adjoint",
-                    help="which measurements to run: single (the headline), batched, adjoint")
+    ap.add_argument("--legs", default="single,batched,adjoint,rebound",
+                    help="which measurements to run: single (the headline), batched, adjoint, rebound")
     ap.add_argument("--secondary-steps", type=int, default=100,
                     help="steps timed for the batched Monte Carlo workload (0 disables it)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -211,6 +251,8 @@ def main():
             out["batched"] = batched_run(args.secondary_steps)
         if "adjoint" in legs:
             out["adjoint"] = adjoint_run()
+        if "rebound" in legs:
+            out["rebound"] = rebound_run()
         print(json.dumps(out), flush=True)
         return
 
@@ -304,6 +346,8 @@ def main():
             out["batched"] = batched_run(args.secondary_steps)
         if "adjoint" in legs:
             out["adjoint"] = adjoint_run()
+        if "rebound" in legs:
+            out["rebound"] = rebound_run()
     if cb is not None:
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline"]["value"] = round(cb["value"], 2)

@@ -102,6 +102,8 @@ typedef struct {
   double soft_tau;     /* smoothed tally time scale, in time steps                      */
   uint32_t flags;      /* DEPO_* switches                                               */
   uint32_t reserved;   /* must be 0                                                     */
+  double u_bulk;       /* bulk (area-mean axial) gas velocity U_b [m/s], used only by the
+                        * capture efficiency of the tally (Eq. CE); 0 = not reported      */
 } depo_params;
 
 /* Per-sample inputs of the uncertainty study (Sections 2.1 and 4.4):
@@ -124,6 +126,9 @@ typedef struct {
   double v_dep_se;    /* Poisson standard error of v_dep                               */
   double j_soft;      /* smoothed deposited mass sum_i m_i (1 - exp(-l_i)) [kg]        */
   int64_t n_alive;    /* particles still suspended                                     */
+  double ce;          /* capture efficiency (4L/D)(u* / U_b) V_dep+ (Eq. CE, D = 2R); with
+                       * DEPO_REBOUND_OSU only sticking impacts deposit, so V_dep+ is the
+                       * paper's V_dep+|stick; 0 when u_bulk = 0                         */
 } depo_tally;
 
 /* Human-readable name of a status code.  Never NULL; static storage. */
@@ -132,7 +137,8 @@ const char *depo_status_string(int status);
 /* Create a context from validated parameters.  Host only, touches no GPU.
  * Returns DEPO_E_INVALID (with *out = NULL) for non-positive or non-finite
  * lengths, densities, viscosity or dt, e_pp outside (0, 1], tau_col_steps < 1,
- * real_bytes not 4 or 8, L < 2R, unknown flag bits or reserved != 0. */
+ * real_bytes not 4 or 8, L < 2R, unknown flag bits, reserved != 0 or a negative or
+ * non-finite u_bulk. */
 depo_status depo_create(const depo_params *p, depo_ctx **out);
 
 /* Destroy a context and its host-side objects (graphs, staging).  Never frees

@@ -186,17 +186,42 @@ def wall_vdw_accel(g, d, A, m, delta_sat):
 
 # ----------------------------------------------------------------------------- rebound law
 
+def yield_stress(T):
+    """Particle yield stress sigma_y(T) = 200 - 0.225 (T - 1000) MPa (Section 4.4), in Pa.
+
+    Reading: floored at 0.  The paper's input theta = 0.225 (T - 1000) / 200 lies in [0, 1], so the
+    law is only defined up to T = 1000 + 200 / 0.225 K, where sigma_y reaches 0; beyond it a negative
+    yield stress would square to a spurious elastic rebound."""
+    return np.maximum(200.0 - 0.225 * (np.asarray(T, dtype=np.float64) - 1000.0), 0.0) * 1e6
+
+
+def temperature_of_theta(theta):
+    """T = 1000 + 200 theta / 0.225 K, the inverse of theta = 0.225 (T - 1000) / 200 (Section 4.4)."""
+    return 1000.0 + 200.0 * np.asarray(theta, dtype=np.float64) / 0.225
+
+
 def osu_rebound_speed_sq(vn1, T, d, m, A, p):
     """Squared rebound normal speed of the temperature-dependent rebound law (Eq. CoR, Section 4.4).
 
-    sigma_y(T) = 200 - 0.225 (T - 1000) MPa, gamma_c = A / (24 pi delta_c^2),
+    sigma_y(T) as ``yield_stress``, gamma_c = A / (24 pi delta_c^2),
     A_cont = acont_coef * pi d^2 / 4.  Reading: the printed CoR does not
     depend on V_n1 for V_n1 below the yield limit (it would exceed 1), so the
     elastic part is capped by the impact energy:
     V_n2^2 = min(V_n1^2, sigma_y^2 / (rho_p E)) - 2 A_cont gamma_c / m.
     The particle sticks when this is <= 0.
     """
-    sigma_y = (200.0 - 0.225 * (T - 1000.0)) * 1e6
+    sigma_y = yield_stress(T)
     gamma_c = A / (24.0 * np.pi * p["delta_c"] ** 2)
     a_cont = p["acont_coef"] * np.pi * d * d / 4.0
     return np.minimum(vn1 * vn1, sigma_y * sigma_y / (p["rho_p"] * p["E_young"])) - 2.0 * a_cont * gamma_c / m
+
+
+def cor_n(vn1, T, d, m, A, p):
+    """Normal coefficient of restitution V_n2 / V_n1 of the rebound law (Eq. CoR); 0 means the particle sticks."""
+    vn2sq = osu_rebound_speed_sq(vn1, T, d, m, A, p)
+    return np.sqrt(np.maximum(vn2sq, 0.0)) / vn1
+
+
+def capture_efficiency(v_dep_plus_stick, L, D, u_star, u_bulk):
+    """CE = (4 L / D) (u* / U_b) V_dep+|stick (Eq. CE): deposited over total particle mass flow rate."""
+    return 4.0 * L / D * u_star / u_bulk * v_dep_plus_stick

@@ -229,9 +229,13 @@ class OracleSim:
             m2 = float(np.sum(self.m[b:e][dep] ** 2))
             vdep = 0.5 * self.R * self.m_dep[s] / self.m_alive_dt[s] if self.m_alive_dt[s] > 0 else 0.0
             se = vdep * np.sqrt(m2) / self.m_dep[s] if self.m_dep[s] > 0 else 0.0
+            # capture efficiency (Eq. CE) as the ratio of mass flow rates: deposition m_dep / t over the
+            # axial flux of the suspended mass at the bulk velocity, (m_alive_dt / t) U_b / L
+            ub = float(self.p.get("u_bulk", 0.0))
+            ce = self.m_dep[s] * self.L / (self.m_alive_dt[s] * ub) if (ub > 0 and self.m_alive_dt[s] > 0) else 0.0
             j_soft = float(np.sum(self.m[b:e] * (-np.expm1(-self.ell[b:e]))))
             out.append(dict(m_dep=float(self.m_dep[s]), n_dep=int(self.n_dep[s]),
                             m_alive_dt=float(self.m_alive_dt[s]), t=self.nstep * self.dt,
                             v_dep=vdep, v_dep_plus=vdep / u_star, v_dep_se=se, j_soft=j_soft,
-                            n_alive=int(np.sum(self.alive[b:e]))))
+                            n_alive=int(np.sum(self.alive[b:e])), ce=float(ce)))
         return out

@@ -510,6 +510,8 @@ template <class Real> depo_status do_tally(depo_ctx *ctx, depo_tally *out, hipSt
     o.v_dep_se = o.m_dep > 0.0 ? o.v_dep * std::sqrt(r[3]) / o.m_dep : 0.0;
     o.j_soft = r[4];
     o.n_alive = (int64_t)std::llround(r[5]);
+    // capture efficiency, Eq. CE
+    o.ce = ctx->p.u_bulk > 0.0 ? 4.0 * ctx->p.L / (2.0 * ctx->p.R) * (us / ctx->p.u_bulk) * o.v_dep_plus : 0.0;
   }
   return check_err<Real>(ctx, s);
 }
@@ -753,6 +755,7 @@ depo_status depo_create(const depo_params *p, depo_ctx **out) {
                   std::isfinite(p->g_body[0]) && std::isfinite(p->g_body[1]) && std::isfinite(p->g_body[2]) &&
                   finite_pos(p->E_young) && finite_pos(p->delta_c) && std::isfinite(p->acont_coef) &&
                   p->acont_coef >= 0.0 && (p->flags & ~kKnownFlags) == 0 && p->reserved == 0 &&
+                  std::isfinite(p->u_bulk) && p->u_bulk >= 0.0 &&
                   (!(p->flags & DEPO_SOFT_TALLY) || (finite_pos(p->soft_eps) && finite_pos(p->soft_tau)));
   if (!ok) return DEPO_E_INVALID;
   depo_ctx *ctx = new depo_ctx();

@@ -95,7 +95,8 @@ __global__ __launch_bounds__(256) void k_prepare(State<Real> st, Phys ph, int mo
           const SampleDev sp = st.samples[s];
           const double ery = y / rho, erz = z / rho;
           const double vn1 = (double)v[1] * ery + (double)v[2] * erz;
-          const double sig = (200.0 - 0.225 * (sp.temperature - 1000.0)) * 1e6;
+          // yield stress floored at zero: theta = 0.225 (T - 1000) / 200 is defined on [0, 1]
+          const double sig = fmax(200.0 - 0.225 * (sp.temperature - 1000.0), 0.0) * 1e6;
           const double gam = sp.hamaker / (24.0 * M_PI * ph.delta_c * ph.delta_c);
           const double acont = ph.acont_coef * M_PI * d * d * 0.25;
           const double m = ph.mass_coef * d * d * d;

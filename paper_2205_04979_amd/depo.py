@@ -42,7 +42,7 @@ class Params(C.Structure):
         ("g_body", C.c_double * 3),
         ("E_young", C.c_double), ("delta_c", C.c_double), ("acont_coef", C.c_double),
         ("soft_eps", C.c_double), ("soft_tau", C.c_double),
-        ("flags", C.c_uint32), ("reserved", C.c_uint32),
+        ("flags", C.c_uint32), ("reserved", C.c_uint32), ("u_bulk", C.c_double),
     ]
 
 
@@ -54,7 +54,7 @@ class Tally(C.Structure):
     _fields_ = [
         ("m_dep", C.c_double), ("n_dep", C.c_int64), ("m_alive_dt", C.c_double), ("t", C.c_double),
         ("v_dep", C.c_double), ("v_dep_plus", C.c_double), ("v_dep_se", C.c_double),
-        ("j_soft", C.c_double), ("n_alive", C.c_int64),
+        ("j_soft", C.c_double), ("n_alive", C.c_int64), ("ce", C.c_double),
     ]
 
 
@@ -124,6 +124,7 @@ def make_params(p: dict, real_bytes: int = 4) -> Params:
             flags |= bit
     out.flags = flags
     out.reserved = 0
+    out.u_bulk = float(p.get("u_bulk") or 0.0)
     return out
 
 

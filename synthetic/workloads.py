@@ -8,7 +8,7 @@ radius R = D/2 = 10 mm and length L = 4 R, and particle sets of 1k to 1M.
 The fluid density is not printed in the paper; 1.2 kg/m^3 reproduces the
 printed tau_p+ values of its three particle sizes (Section 2.1).  The time
 step is 1e-4 of the response time of a 10 um, 1000 kg/m^3 particle for every
-workload.
+workload but the temperature study.
 
 Workloads (name: content):
 
@@ -22,6 +22,13 @@ Workloads (name: content):
   rebound law on; 1,000 steps.
 * ``adjoint-64x16k``: 64 samples of 16,384 particles, parameters drawn as in
   ``batched-256``; smoothed deposition tally; 100 steps.
+* ``rebound-theta-64``: the temperature study of Section 4.4: 64 samples of
+  16,384 particles, xi and zeta as in ``batched-256``, theta ~ U[0, 1]
+  (T = 1000 + 200 theta / 0.225 K, 1000 to 1889 K), rebound law on with a
+  wall contact area of 1e-3 of the particle cross-section, 128^3 field,
+  dt = 1e-5 s (0.05 viscous time units, so that 1,000 steps span ~50 of
+  them and several percent of the particles reach the wall); its quantity
+  of interest is the capture efficiency.
 * ``large-1m``: 1,048,576 particles, d in {1, 5, 10, 20} um equal mix,
   q ~ N(0, (2e-15 C)^2), A = 5e-20 J, 256^3 field at Re_tau = 300, 500 steps.
 
@@ -59,11 +66,16 @@ def physical_params(re_tau: float = 180.0, **overrides) -> dict:
         drag=True, coulomb=True, collide=True, vdw=True, vdw_gu=True,
         wall_image=True, wall_vdw=True,
         rebound_osu=False, soft_tally=False, body_force=False,
+        u_bulk=None,
     )
     for k, v in overrides.items():
         if k not in p:
             raise KeyError(f"unknown parameter {k!r}")
         p[k] = v
+    if p["u_bulk"] is None:
+        # bulk velocity of the synthetic field's mean profile (its fluctuations have zero mean)
+        from .field import bulk_velocity_plus
+        p["u_bulk"] = bulk_velocity_plus(p["re_tau"]) * p["re_tau"] * p["nu"] / p["R"]
     return p
 
 
@@ -133,12 +145,15 @@ def _single_65k(n=65536, steps=2000, field_n=128, seed=2, **kw):
     return Workload("single-65k", p, field_n, 180, steps, np.array([0, n], np.int64), sp, x, d, qb)
 
 
-def _mc_batch(name, seed, n_samples, n_lo, n_hi, steps, field_n, fixed_n=None, **kw):
+def _mc_batch(name, seed, n_samples, n_lo, n_hi, steps, field_n, fixed_n=None, theta_range=False, **kw):
     rng = np.random.default_rng(seed)
     p = physical_params(180.0, **kw)
     xi = rng.uniform(0.0, 0.1, n_samples)
     zeta = rng.uniform(0.0, 1.0, n_samples)
-    temp = rng.uniform(280.0, 360.0, n_samples)
+    if theta_range:
+        temp = 1000.0 + 200.0 * rng.uniform(0.0, 1.0, n_samples) / 0.225
+    else:
+        temp = rng.uniform(280.0, 360.0, n_samples)
     if fixed_n is None:
         ns = rng.integers(n_lo, n_hi + 1, n_samples)
     else:
@@ -176,12 +191,21 @@ def _large_1m(n=1 << 20, steps=500, field_n=256, seed=5, **kw):
     return Workload("large-1m", p, field_n, 300, steps, np.array([0, n], np.int64), sp, x, d, qb)
 
 
+def _rebound_theta_64(n_samples=64, n_per=16384, steps=1000, field_n=128, seed=6, **kw):
+    kw.setdefault("rebound_osu", True)
+    kw.setdefault("acont_coef", 1e-3)
+    kw.setdefault("dt", 1e-5)
+    return _mc_batch("rebound-theta-64", seed, n_samples, 0, 0, steps, field_n, fixed_n=n_per,
+                     theta_range=True, **kw)
+
+
 WORKLOADS = {
     "plain-1k": _plain_1k,
     "single-65k": _single_65k,
     "batched-256": _batched_256,
     "adjoint-64x16k": _adjoint_64x16k,
     "large-1m": _large_1m,
+    "rebound-theta-64": _rebound_theta_64,
 }
 
 

@@ -68,7 +68,8 @@ def test_status_strings(depo):
 
 
 @pytest.mark.parametrize("key,value", [("R", 0.0), ("L", -1.0), ("nu", float("nan")), ("dt", 0.0),
-                                       ("e_pp", 1.5), ("tau_col_steps", 0), ("eps0", float("inf"))])
+                                       ("e_pp", 1.5), ("tau_col_steps", 0), ("eps0", float("inf")),
+                                       ("u_bulk", -1.0), ("u_bulk", float("nan"))])
 def test_create_rejects_bad_params(depo, key, value):
     p = physical_params()
     p[key] = value
