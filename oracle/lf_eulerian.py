@@ -72,8 +72,9 @@ def momentum(y, Phi, work, tau1):
         h = y[k] - y[k - 1]
         rhs = K + (Phi[k] - Phi[k - 1]) + work[k - 1]
         if rhs > 0.0:
+            # positive root of v^2/2 + a v = rhs, written without the cancellation of -a + sqrt(a^2 + 2 rhs)
             a = h / tau1
-            v = -a + math.sqrt(a * a + 2.0 * rhs)
+            v = 2.0 * rhs / (a + math.sqrt(a * a + 2.0 * rhs))
         else:
             v = 0.0
         V[k - 1] = v
@@ -123,8 +124,9 @@ def solve(params, d, q, A, n_wall=800, n_core=800, return_profiles=False):
     # gaps (y - d/2) in wall units: geometric from the 1e-12 m floor to 1, then uniform to the centre
     gw = np.geomspace(G_MIN / lw, 1.0, n_wall)
     gc = np.linspace(1.0, yc - yw, n_core + 1)[1:]
-    y = yw + np.concatenate([gw, gc])             # increasing: wall -> centre
-    gap = (y - yw) * lw                           # metres
+    g = np.concatenate([gw, gc])                  # gap in wall units
+    y = yw + g                                    # increasing: wall -> centre
+    gap = g * lw                                  # metres (from g itself: y - yw would round away the 1e-12 m gaps)
     ym = y * lw
     Phi = Rr * vfy_plus(y) ** 2
     E = k_e * q * q / (4.0 * m)                   # image:  F = -E / y^2   [m^3/s^2]

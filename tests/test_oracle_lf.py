@@ -77,3 +77,12 @@ def test_constant_flux_profile_and_grid_convergence():
     a = lf.solve(p, d, 0.1 * q_max_charge(d), 1e-18, n_wall=1600, n_core=1600)
     b = lf.solve(p, d, 0.1 * q_max_charge(d), 1e-18, n_wall=6400, n_core=6400)
     assert abs(a - b) / b < 0.02
+
+
+def test_momentum_heavy_drag_equilibrium():
+    """Drag time far below the cell transit time (tiny particles): V = tau G still, to rounding; the
+    cancellation-prone root -a + sqrt(a^2 + 2 rhs) would return 0 here."""
+    y = np.linspace(0.0, 100.0, 20001)
+    G, tau = 0.004, 1e-6
+    V = lf.momentum(y, np.zeros_like(y), G * np.diff(y), tau)
+    assert np.isclose(V[0], tau * G, rtol=1e-6)
