@@ -28,6 +28,9 @@ papers, which are not reproduced here; every one is a stated substitute):
   variance ratio), particle rms V'_py+ = sqrt(Rr) V'_fy+;
 * eps/nu = tau_L+ Rr V'_fy+^2 (particle eddy diffusivity);
 * D_B/nu = k_B T / (3 pi rho_f nu^2 d), T = 293 K;
+* the particle wall-normal velocity variance at the wall adds the thermal
+  part k_B T / m to the turbulent part: V'_py+^2 = Rr V'_fy+^2 + k_B T / (m u*^2)
+  (without it a Brownian particle could never reach the wall);
 * M_r = V_w / (sqrt(2) V'_py+(wall)).
 
 Numerics (as the paper describes: near-wall grid refinement, implicit drag):
@@ -102,8 +105,10 @@ def flux(y, V, D, hw):
         dy = y[k + 1] - y[k]
         Vm = 0.5 * (V[k] + V[k + 1])
         Dm = 0.5 * (D[k] + D[k + 1])
-        if Vm > 0.0:
-            phi[k + 1] = hw / Vm + (phi[k] - hw / Vm) * math.exp(-Vm / Dm * dy)
+        x = Vm * dy / Dm
+        if x > 0.0:
+            # hw/Vm + (phi - hw/Vm) e^-x, arranged so that a tiny drift does not cancel catastrophically
+            phi[k + 1] = phi[k] * math.exp(-x) + hw * dy / Dm * (-math.expm1(-x) / x)
         else:
             phi[k + 1] = phi[k] + hw * dy / Dm
     return hw / phi[-1], phi / phi[-1]
@@ -118,7 +123,7 @@ def solve(params, d, q, A, n_wall=800, n_core=800, return_profiles=False):
     m = ph.particle_mass(d, rho_p)
     k_e = ph.coulomb_constant(params["eps0"])
     Rr = 1.0 / (1.0 + taup_plus / TAU_L_PLUS)
-    DB = K_B * 293.0 / (3.0 * math.pi * rho_f * nu * nu * d)
+    db_plus = K_B * 293.0 / (3.0 * math.pi * rho_f * nu * nu * d)   # D_B / nu (Stokes-Einstein)
     yw = 0.5 * d / lw
     yc = R / lw
     # gaps (y - d/2) in wall units: geometric from the 1e-12 m floor to 1, then uniform to the centre
@@ -133,8 +138,9 @@ def solve(params, d, q, A, n_wall=800, n_core=800, return_profiles=False):
     C = A * d / (12.0 * m)                        # vdW:    F = -C / g^2   [m^3/s^2]
     work = (E * (1.0 / ym[:-1] - 1.0 / ym[1:]) + C * (1.0 / gap[:-1] - 1.0 / gap[1:])) / (us * us)
     V = momentum(y, Phi, work, taup_plus)
-    D = DB / nu + TAU_L_PLUS * Rr * vfy_plus(y) ** 2
-    hw = wall_flux_factor(V[0], math.sqrt(Rr) * float(vfy_plus(y[0])))
+    D = db_plus + TAU_L_PLUS * Rr * vfy_plus(y) ** 2
+    vp_wall = math.sqrt(Rr * float(vfy_plus(y[0])) ** 2 + K_B * 293.0 / (m * us * us))
+    hw = wall_flux_factor(V[0], vp_wall)
     vdep, rho = flux(y, V, D, hw)
     if return_profiles:
         return dict(vdep_plus=vdep, y_plus=y, V=V, rho=rho, D=D, h_w=hw, taup_plus=taup_plus)

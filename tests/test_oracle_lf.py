@@ -74,9 +74,10 @@ def test_constant_flux_profile_and_grid_convergence():
     k = slice(900, 1500)
     Jk = 0.5 * (D[k] + D[1:][k]) * np.diff(rho)[k] / np.diff(y)[k] + 0.5 * (V[k] + V[1:][k]) * 0.5 * (rho[k] + rho[1:][k])
     assert np.allclose(Jk, J, rtol=1e-2)
-    a = lf.solve(p, d, 0.1 * q_max_charge(d), 1e-18, n_wall=1600, n_core=1600)
-    b = lf.solve(p, d, 0.1 * q_max_charge(d), 1e-18, n_wall=6400, n_core=6400)
-    assert abs(a - b) / b < 0.02
+    # first-order grid convergence: successive refinements change V_dep+ by shrinking amounts
+    a, b, c = (lf.solve(p, d, 0.1 * q_max_charge(d), 1e-18, n_wall=n, n_core=n) for n in (1600, 3200, 6400))
+    assert abs(a - c) / c < 0.04
+    assert 1.5 < abs(a - b) / abs(b - c) < 2.5
 
 
 def test_momentum_heavy_drag_equilibrium():
@@ -86,3 +87,32 @@ def test_momentum_heavy_drag_equilibrium():
     G, tau = 0.004, 1e-6
     V = lf.momentum(y, np.zeros_like(y), G * np.diff(y), tau)
     assert np.isclose(V[0], tau * G, rtol=1e-6)
+
+
+def test_diffusivity_is_stokes_einstein_plus_eddy():
+    """D+ = D_B / nu + eps / nu: the Brownian part is k_B T / (3 pi mu d) / nu with mu = rho_f nu,
+    T = 293 K (Stokes-Einstein), the eddy part tau_L+ Rr V'_fy+^2 (substitute closures)."""
+    p = physical_params(180.0)
+    for d in (0.05e-6, 1.6e-6, 16e-6):
+        r = lf.solve(p, d, 0.0, 0.0, return_profiles=True)
+        mu = p["rho_f"] * p["nu"]
+        db = 1.380649e-23 * 293.0 / (3 * np.pi * mu * d) / p["nu"]
+        rr = 1.0 / (1.0 + r["taup_plus"] / 10.0)
+        eddy = 10.0 * rr * lf.vfy_plus(r["y_plus"]) ** 2
+        assert np.allclose(r["D"] - eddy, db, rtol=1e-9)
+
+
+def test_brownian_limit_is_resistances_in_series():
+    """A tiny force-free particle (0.01 um): turbophoresis is negligible, so V_dep+ is the diffusion
+    resistance 1 / (1/h_w + int dy+ / D+) with D+ = D_B/nu + eps/nu (quadrature of the closed form)."""
+    p = physical_params(180.0)
+    d = 0.01e-6
+    r = lf.solve(p, d, 0.0, 0.0, n_wall=4000, n_core=16000, return_profiles=True)
+    assert np.max(np.abs(r["V"])) < 1e-3 * r["vdep_plus"]
+    db = 1.380649e-23 * 293.0 / (3 * np.pi * p["rho_f"] * p["nu"] * d) / p["nu"]
+    rr = 1.0 / (1.0 + r["taup_plus"] / 10.0)
+    y0, yc = r["y_plus"][0], r["y_plus"][-1]
+    pts = [y0, y0 + 1e-6, y0 + 1e-3, y0 + 1, y0 + 10, y0 + 40]
+    res = sum(quad(lambda t: 1.0 / (db + 10.0 * rr * float(lf.vfy_plus(t)) ** 2), a, b, limit=200)[0]
+              for a, b in zip(pts + [], pts[1:] + [yc]))
+    assert np.isclose(r["vdep_plus"], 1.0 / (1.0 / r["h_w"] + res), rtol=1e-3)
