@@ -219,6 +219,43 @@ def rebound_run() -> dict:
     return res
 
 
+def lf_run() -> dict:
+    """The low-fidelity model (Appendix B) over the LF-only Monte Carlo budget of Table 3 at p = 36:
+    25,920 particle classes (d in {1.6, 5, 16} um, xi ~ U[0, 0.1], zeta ~ U[0, 1]) per launch."""
+    import torch
+    from paper_2205_04979_amd.depo import lf_solve
+    from synthetic.workloads import physical_params, q_max
+    rng = np.random.default_rng(11)
+    n = 25920
+    p = physical_params(180.0)
+    d = rng.choice([1.6e-6, 5e-6, 16e-6], n)
+    q = rng.uniform(0, 0.1, n) * q_max(d)
+    A = rng.uniform(0, 1, n) * 1e-18
+    dev = [torch.from_numpy(a).to("cuda:0") for a in (d, q, A)]
+    out = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    from paper_2205_04979_amd import depo as dp
+    import ctypes as C
+    cp = dp.make_params(p)
+    args = [C.byref(cp), n] + [C.c_void_p(t.data_ptr()) for t in dev] + [800, 800, C.c_void_p(out.data_ptr()),
+                                                                         C.c_void_p(torch.cuda.current_stream().cuda_stream)]
+    L = dp.lib()
+    assert L.depo_lf_solve(*args) == 0
+    torch.cuda.synchronize()
+    reps = 5
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        assert L.depo_lf_solve(*args) == 0
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    res = {"classes": n, "nodes": 1600, "ms_per_launch": round(ms, 4), "classes_per_s": round(n / (ms * 1e-3), 1),
+           "vdep_plus_median": float(np.median(out.cpu().numpy())),
+           "note": "one lane per class, single inward pass (momentum march with the flux carried as an affine map)"}
+    log(f"[bench] lf: {res}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,8 +266,8 @@ def main():
     ap.add_argument("--cpu-targets", type=int, default=4096)
     ap.add_argument("--kernel", default=None, help="pair-kernel shape ipl,waves,block (skips autotuning)")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--legs", default="single,batched,adjoint,rebound",
-                    help="which measurements to run: single (the headline), batched, adjoint, rebound")
+    ap.add_argument("--legs", default="single,batched,adjoint,rebound,lf",
+                    help="which measurements to run: single (the headline), batched, adjoint, rebound, lf")
     ap.add_argument("--secondary-steps", type=int, default=100,
                     help="steps timed for the batched Monte Carlo workload (0 disables it)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -253,6 +290,8 @@ def main():
             out["adjoint"] = adjoint_run()
         if "rebound" in legs:
             out["rebound"] = rebound_run()
+        if "lf" in legs:
+            out["lf"] = lf_run()
         print(json.dumps(out), flush=True)
         return
 
@@ -348,6 +387,8 @@ def main():
             out["adjoint"] = adjoint_run()
         if "rebound" in legs:
             out["rebound"] = rebound_run()
+        if "lf" in legs:
+            out["lf"] = lf_run()
     if cb is not None:
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline"]["value"] = round(cb["value"], 2)

@@ -257,6 +257,31 @@ depo_status depo_adjoint_workspace_bytes(const depo_ctx *ctx, int32_t n_steps, i
 depo_status depo_adjoint(depo_ctx *ctx, int32_t n_steps, int32_t ckpt_every, const double *h_weights,
                          double *h_grad, void *d_adj_work, size_t bytes, depo_stream stream);
 
+/* Low-fidelity model: the one-dimensional Eulerian deposition model of
+ * Appendix B (particle momentum equation with turbophoresis, image-charge and
+ * wall-cohesion forces, Eq. mom_modified with implicit drag; constant-flux
+ * equation, Eq. continuity, with a kinetic wall condition) for n particle
+ * classes, one V_dep+ per class, in FP64.  The paper leaves the closures to
+ * other publications; this model uses stated substitutes: tau_1+ = tau_p+,
+ * V'_fy+ = 0.005 y+^2 / (1 + 0.002923 y+^2.128), Rr = 1/(1 + tau_p+/10),
+ * eps/nu = 10 Rr V'_fy+^2, Stokes-Einstein D_B at 293 K, wall velocity
+ * variance Rr V'_fy+^2 + k_B T/(m u*^2), half-Maxwellian wall flux.
+ *
+ * p: only R, nu, rho_f, rho_p, re_tau and eps0 are used (each finite and
+ *   positive, else DEPO_E_INVALID); no context is needed.
+ * d_diam, d_charge, d_hamaker: DEVICE arrays of n doubles (diameter [m],
+ *   charge [C], Hamaker constant [J]) per class; d_vdep_plus: DEVICE array of
+ *   n doubles, written.  All caller-owned.  A class with a non-positive or
+ *   non-finite diameter or a non-finite charge or Hamaker constant gets NaN.
+ * n_wall >= 2 nodes span the gap from 1e-12 m to one wall unit geometrically;
+ *   n_core >= 1 more nodes reach the pipe centre uniformly.
+ * n = 0 is a no-op.  Asynchronous on `stream` (does not synchronise).  Errors
+ * are reported through the status only (there is no context for
+ * depo_last_error). */
+depo_status depo_lf_solve(const depo_params *p, int64_t n, const double *d_diam, const double *d_charge,
+                          const double *d_hamaker, int32_t n_wall, int32_t n_core, double *d_vdep_plus,
+                          depo_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

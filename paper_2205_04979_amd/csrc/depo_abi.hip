@@ -986,5 +986,19 @@ depo_status depo_adjoint(depo_ctx *ctx, int32_t n_steps, int32_t ckpt_every, con
   return DISPATCH(do_adjoint, ctx, n_steps, ckpt_every, h_weights, h_grad, d_adj_work, bytes, (hipStream_t)stream);
 }
 
+depo_status depo_lf_solve(const depo_params *p, int64_t n, const double *d_diam, const double *d_charge,
+                          const double *d_hamaker, int32_t n_wall, int32_t n_core, double *d_vdep_plus,
+                          depo_stream stream) {
+  if (!p || n < 0 || n_wall < 2 || n_core < 1) return DEPO_E_INVALID;
+  if (!(finite_pos(p->R) && finite_pos(p->nu) && finite_pos(p->rho_f) && finite_pos(p->rho_p) &&
+        finite_pos(p->re_tau) && finite_pos(p->eps0)))
+    return DEPO_E_INVALID;
+  if (n == 0) return DEPO_OK;
+  if (!d_diam || !d_charge || !d_hamaker || !d_vdep_plus) return DEPO_E_INVALID;
+  const LfConst c{p->R, p->nu, p->rho_f, p->rho_p, p->re_tau, p->eps0, n_wall, n_core};
+  launch_lf(c, n, d_diam, d_charge, d_hamaker, d_vdep_plus, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? DEPO_OK : DEPO_E_HIP;
+}
+
 }  // extern "C"
 

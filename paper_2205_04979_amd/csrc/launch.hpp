@@ -32,4 +32,12 @@ void launch_coulomb(const State<Real> &st, const Phys &ph, int n_tiles, const Co
 int coulomb_tile_targets(const CoulombConfig &cfg);
 bool coulomb_config_supported(int real_bytes, const CoulombConfig &cfg);
 
+// One-dimensional Eulerian low-fidelity model, one lane per particle class.
+struct LfConst {
+  double R, nu, rho_f, rho_p, re_tau, eps0;
+  int n_wall, n_core;
+};
+void launch_lf(const LfConst &c, int64_t n, const double *d, const double *q, const double *A, double *out,
+               hipStream_t s);
+
 }  // namespace depo

@@ -84,6 +84,7 @@ _SIGS = {
     "depo_state_upload": (C.c_int, [_P, _P, C.c_size_t, _P]),
     "depo_adjoint_workspace_bytes": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
     "depo_adjoint": (C.c_int, [_P, C.c_int32, C.c_int32, _DP, _DP, _P, C.c_size_t, _P]),
+    "depo_lf_solve": (C.c_int, [C.POINTER(Params), C.c_int64, _P, _P, _P, C.c_int32, C.c_int32, _P, _P]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -298,6 +299,24 @@ class Simulation(Context):
                                         C.c_void_p(aligned), n.value, self._stream(stream)), "depo_adjoint")
         del ws
         return g
+
+
+def lf_solve(params: dict, d, q, A, n_wall: int = 800, n_core: int = 800, device: str = "cuda:0") -> np.ndarray:
+    """V_dep+ of the one-dimensional Eulerian low-fidelity model for each particle class (d[i], q[i], A[i]).
+
+    Moves the three arrays to the device, runs ``depo_lf_solve`` on the current stream and copies the result back."""
+    import torch
+    d, q, A = (np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), np.shape(d))).ravel()
+               for a in (d, q, A))
+    n = d.shape[0]
+    dev = [torch.from_numpy(a.copy()).to(device) for a in (d, q, A)]
+    out = torch.empty(n, dtype=torch.float64, device=device)
+    cp = make_params(params)
+    st = lib().depo_lf_solve(C.byref(cp), n, *(C.c_void_p(t.data_ptr()) for t in dev), int(n_wall), int(n_core),
+                             C.c_void_p(out.data_ptr()), C.c_void_p(_stream_handle(None)))
+    if st != 0:
+        raise DepoError(st, "depo_lf_solve: invalid arguments" if st == -1 else "depo_lf_solve failed")
+    return out.cpu().numpy()
 
 
 def _autograd_function():

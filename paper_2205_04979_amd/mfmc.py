@@ -13,6 +13,8 @@
 * ``HighFidelityGPU``: evaluates V_dep+ for many input points (charge scale xi,
   Hamaker ratio zeta, temperature) as ONE batched launch of the particle step,
   one Monte Carlo sample per input point;
+* ``LowFidelityGPU``: the one-dimensional Eulerian model (Appendix B) for the
+  same inputs, one lane per input point;
 * ``mfmc_sobol``: the full estimator pipeline (pilot statistics in, budget
   split p_eff = p / (d + 2), HF and LF runs on nested samples, MF mean,
   variance, main and total indices).
@@ -138,6 +140,29 @@ class HighFidelityGPU:
         out = np.array([t["v_dep_plus"] for t in sim.tally()])
         sim.close()
         return out
+
+
+@dataclass
+class LowFidelityGPU:
+    """V_dep+ of the one-dimensional Eulerian model (Appendix B) for one particle size, as the cheap model.
+
+    Each input row (xi, zeta[, T]) gives the charge xi * q_max(d) (Eq. 1) and the Hamaker constant
+    zeta * A0; the model is isothermal, so a temperature column is ignored.  All rows are solved by one
+    launch, one lane per row."""
+
+    params: dict
+    d: float
+    a0: float = 1e-18
+    n_wall: int = 800
+    n_core: int = 800
+
+    def __call__(self, inputs: np.ndarray) -> np.ndarray:
+        from .depo import lf_solve
+        inputs = np.atleast_2d(np.asarray(inputs, dtype=np.float64))
+        S = inputs.shape[0]
+        d = np.full(S, float(self.d))
+        q = inputs[:, 0] * 500.0 * 1.6e-19 * (d / 1e-6) ** 2
+        return lf_solve(self.params, d, q, inputs[:, 1] * self.a0, self.n_wall, self.n_core)
 
 
 # ------------------------------------------------------------------ pipeline

@@ -162,3 +162,20 @@ def test_adjoint_host_validation(depo):
     w = (C.c_double * 2)(1.0, 1.0)
     g = (C.c_double * 6)()
     assert L.depo_adjoint(ctx._h, 10, 5, w, g, C.c_void_p(256), 1 << 30, None) == depo.E_STATE  # not seeded
+
+
+def test_lf_solve_host_validation(depo):
+    """The low-fidelity entry point checks its parameters and sizes before touching the device."""
+    L = depo.lib()
+    cp = depo.make_params(physical_params())
+    nul = C.c_void_p(0)
+    fake = C.c_void_p(256)
+    assert L.depo_lf_solve(C.byref(cp), 0, nul, nul, nul, 800, 800, nul, None) == depo.OK      # empty batch
+    assert L.depo_lf_solve(C.byref(cp), 4, nul, fake, fake, 800, 800, fake, None) == depo.E_INVALID
+    assert L.depo_lf_solve(C.byref(cp), -1, fake, fake, fake, 800, 800, fake, None) == depo.E_INVALID
+    assert L.depo_lf_solve(C.byref(cp), 4, fake, fake, fake, 1, 800, fake, None) == depo.E_INVALID
+    assert L.depo_lf_solve(C.byref(cp), 4, fake, fake, fake, 800, 0, fake, None) == depo.E_INVALID
+    assert L.depo_lf_solve(None, 4, fake, fake, fake, 800, 800, fake, None) == depo.E_INVALID
+    for key, value in (("nu", 0.0), ("re_tau", float("nan")), ("eps0", -1.0)):
+        bad = depo.make_params(dict(physical_params(), **{key: value}))
+        assert L.depo_lf_solve(C.byref(bad), 4, fake, fake, fake, 800, 800, fake, None) == depo.E_INVALID
