@@ -195,15 +195,25 @@ depo_status depo_step(depo_ctx *ctx, int32_t n_steps, depo_stream stream);
  * in milliseconds.  1 <= n_steps <= 100000.  Synchronises the stream. */
 depo_status depo_step_timed(depo_ctx *ctx, int32_t n_steps, depo_stream stream, double *h_phase_ms);
 
+/* Pair-kernel modes (depo_set_kernel_config). */
+enum {
+  DEPO_PAIR_PLAIN = 0,      /* one-sided sums, plain accumulation                          */
+  DEPO_PAIR_KAHAN = 1,      /* one-sided sums, Kahan-compensated block accumulation        */
+  DEPO_PAIR_SYMMETRIC = 2   /* FP32 only: every unordered pair once, the reaction applied to
+                             * the source (Newton's third law); Kahan on the target side,
+                             * FP64 combination of per-tile partials                        */
+};
+
 /* Choose the Coulomb pair-kernel shape (targets per lane, wavefronts per
- * workgroup, sources per block, Kahan-compensated block accumulation on/off)
- * and whether depo_step replays a captured HIP graph (use_graph != 0, the
- * default) or launches kernels directly.  DEPO_E_INVALID for a shape that is
- * not compiled in.  Defaults: (1, 8, 32, compensated) in FP32, (1, 4, 16,
- * plain) in FP64; block 64 selects the variant that prefetches source records
- * one group ahead. */
+ * workgroup, sources per block, mode DEPO_PAIR_*) and whether depo_step
+ * replays a captured HIP graph (use_graph != 0, the default) or launches
+ * kernels directly.  DEPO_E_INVALID for a shape that is not compiled in.
+ * Defaults: (1, 8, 32, DEPO_PAIR_KAHAN) in FP32, (1, 4, 16, DEPO_PAIR_PLAIN) in
+ * FP64; block 64 selects the one-sided variant that prefetches source records
+ * one group ahead.  The symmetric mode takes block = 64 (sources are paired in
+ * rounds of 64) and items of 64 * targets_per_lane * waves >= 256 targets. */
 depo_status depo_set_kernel_config(depo_ctx *ctx, int32_t targets_per_lane, int32_t waves, int32_t block,
-                                   int32_t compensated, int32_t use_graph);
+                                   int32_t mode, int32_t use_graph);
 
 /* Recompute the non-drag acceleration of every alive particle at the
  * current positions and velocities (the force evaluation of a step without

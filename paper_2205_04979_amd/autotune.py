@@ -16,6 +16,9 @@ from typing import Optional
 
 FP32_SHAPES = [(1, 4, 32), (1, 8, 32), (1, 16, 32), (2, 4, 32), (2, 8, 32), (2, 16, 32), (4, 4, 32), (4, 8, 32),
                (1, 4, 64), (1, 8, 64), (1, 16, 64), (2, 8, 64), (2, 16, 64)]
+# symmetric pair kernel (mode 2): (targets per lane, waves, 64-source rounds, 2); 64 IPL W targets per item
+FP32_SYM_SHAPES = [(1, 4, 64, 2), (1, 8, 64, 2), (2, 2, 64, 2), (2, 4, 64, 2), (4, 1, 64, 2), (4, 2, 64, 2),
+                   (4, 4, 64, 2), (8, 1, 64, 2)]
 FP64_SHAPES = [(1, 4, 16), (1, 8, 16), (2, 4, 16)]
 
 
@@ -36,11 +39,16 @@ def autotune(sim, steps: int = 3, cache_path: Optional[str] = None, verbose: boo
             best = tuple(cache[key]["best"])
             sim.set_kernel_config(*best)
             return best, {tuple(json.loads(k)): v for k, v in cache[key]["ms"].items()}
-    shapes = FP32_SHAPES if sim.real_bytes == 4 else FP64_SHAPES
+    shapes = FP32_SHAPES + FP32_SYM_SHAPES if sim.real_bytes == 4 else FP64_SHAPES
     blob = sim.state_download()
     times = {}
     for shp in shapes:
-        sim.set_kernel_config(*shp)
+        try:
+            sim.set_kernel_config(*shp)
+        except Exception as exc:      # a symmetric shape the layout's partial arrays do not cover
+            if verbose:
+                print(f"[autotune] shape {shp} skipped: {exc}", flush=True)
+            continue
         sim.step_timed(1)                       # first launch of a shape: code object load
         sim.state_upload(blob)
         ms = sim.step_timed(steps)["coulomb"] / steps

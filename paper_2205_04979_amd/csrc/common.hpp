@@ -45,6 +45,13 @@ struct SampleDev {
 // sources are [j0, j0+jcount).
 struct TileDev { int32_t i0, icount, j0, jcount; };
 
+// One work item of the symmetric pair kernel: targets [i0, i0+icount) against
+// sources [j0, j0+jcount) of sample `sample`.  A diagonal item (j0 == i0) forms
+// all ordered pairs of its tile on the target side and applies no reaction.
+struct __align__(32) SymItem {
+  int32_t i0, icount, j0, jcount, sample, pad[3];
+};
+
 // Per-launch constants, all in double; kernels convert to the working type.
 struct Phys {
   int32_t N, S, nx, ny, nz;
@@ -89,6 +96,9 @@ struct State {
   Real *jr;                       // radius in units of the x quantum
   SampleDev *samples;
   TileDev *tiles;
+  SymItem *items;                 // symmetric pair-kernel work items (FP32 only)
+  double *fx_scale;               // [S] fixed-point units per unit of pair sum, per sample
+  unsigned long long *accx, *accy, *accz;  // [N] fixed-point pair-sum accumulators (zero between steps)
   typename Prec<Real>::Vec4 *field;
   int32_t *nstep;
   uint32_t *err;

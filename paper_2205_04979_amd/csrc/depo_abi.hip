@@ -18,6 +18,8 @@
 
 using namespace depo;
 
+constexpr int kSymTileMin = 256;   // smallest symmetric pair-kernel item (64 * ipl * waves targets)
+
 namespace {
 
 constexpr uint32_t kKnownFlags = (1u << 10) - 1;
@@ -66,6 +68,11 @@ struct depo_ctx {
   int64_t cell_cap = 0;
   int scan_blocks = 0;
   int tile_cap = 0;
+  // symmetric pair kernel (FP32): item capacity (for the smallest item size),
+  // item counts, per-sample bounds for the fixed-point scale
+  int64_t sym_cap = 0;
+  int n_diag = 0, n_off = 0;
+  std::vector<double> sum_abs_qb, dmin;
   // workspace
   size_t ws_need = 0;
   char *ws = nullptr;
@@ -143,6 +150,12 @@ size_t carve(depo_ctx *ctx, char *base, State<Real> &st) {
   st.js = (JSrc<Real> *)take(N * sizeof(JSrc<Real>));
   st.samples = (SampleDev *)take((size_t)ctx->S * sizeof(SampleDev));
   st.tiles = (TileDev *)take((size_t)std::max(ctx->tile_cap, 1) * sizeof(TileDev));
+  const size_t nacc = sizeof(Real) == 4 ? N : 1;   // fixed-point accumulators: FP32 form only
+  st.items = (SymItem *)take((size_t)std::max<int64_t>(ctx->sym_cap, 1) * sizeof(SymItem));
+  st.fx_scale = (double *)take((size_t)ctx->S * sizeof(double));
+  st.accx = (unsigned long long *)take(nacc * 8);
+  st.accy = (unsigned long long *)take(nacc * 8);
+  st.accz = (unsigned long long *)take(nacc * 8);
   st.field = (typename Prec<Real>::Vec4 *)take((size_t)ctx->nx * ctx->ny * ctx->nz * sizeof(typename Prec<Real>::Vec4));
   st.nstep = (int32_t *)take(64);
   st.err = (uint32_t *)take(64);
@@ -208,13 +221,91 @@ void build_tiles(depo_ctx *ctx, std::vector<TileDev> &tiles) {
   }
 }
 
+// Work items of the symmetric pair kernel for item size T: per sample, the n_t
+// diagonal items, then the n_t (n_t - 1) / 2 items above the diagonal.
+void build_items(const depo_ctx *ctx, int T, std::vector<SymItem> &items, int &n_diag, int &n_off) {
+  std::vector<SymItem> diag, off;
+  for (int s = 0; s < ctx->S; ++s) {
+    const int64_t b = ctx->off[s], n = ctx->off[s + 1] - b;
+    const int64_t nt = (n + T - 1) / T;
+    auto cnt = [&](int64_t I) { return (int32_t)std::min<int64_t>(T, n - I * T); };
+    for (int64_t I = 0; I < nt; ++I) {
+      const int32_t i0 = (int32_t)(b + I * T);
+      diag.push_back(SymItem{i0, cnt(I), i0, cnt(I), s, {0, 0, 0}});
+      for (int64_t J = I + 1; J < nt; ++J)
+        off.push_back(SymItem{i0, cnt(I), (int32_t)(b + J * T), cnt(J), s, {0, 0, 0}});
+    }
+  }
+  // costliest items first
+  auto by_cost = [](const SymItem &a, const SymItem &c) {
+    return (int64_t)a.icount * a.jcount > (int64_t)c.icount * c.jcount;
+  };
+  std::stable_sort(diag.begin(), diag.end(), by_cost);
+  std::stable_sort(off.begin(), off.end(), by_cost);
+  n_diag = (int)diag.size();
+  n_off = (int)off.size();
+  items = diag;
+  items.insert(items.end(), off.begin(), off.end());
+}
+
+// Upload the symmetric work items for the current configuration.
+depo_status upload_items(depo_ctx *ctx) {
+  std::vector<SymItem> items;
+  build_items(ctx, coulomb_sym_tile(ctx->ccfg), items, ctx->n_diag, ctx->n_off);
+  if ((int64_t)items.size() > ctx->sym_cap) return ctx->fail(DEPO_E_CAPACITY, "symmetric item list exceeds capacity");
+  if (!items.empty()) HIP_TRY(hipMemcpy(ctx->sf.items, items.data(), items.size() * sizeof(SymItem), hipMemcpyHostToDevice));
+  return DEPO_OK;
+}
+
+// Per-sample sum of |qbase| and smallest diameter (host copies of the seeded arrays).
+void set_charge_bounds(depo_ctx *ctx, const double *h_d, const double *h_qb) {
+  ctx->sum_abs_qb.assign(ctx->S, 0.0);
+  ctx->dmin.assign(ctx->S, 0.0);
+  for (int s = 0; s < ctx->S; ++s) {
+    double sq = 0.0, dm = INFINITY;
+    for (int64_t i = ctx->off[s]; i < ctx->off[s + 1]; ++i) {
+      sq += std::fabs(h_qb[i]);
+      dm = std::min(dm, h_d[i]);
+    }
+    ctx->sum_abs_qb[s] = sq;
+    ctx->dmin[s] = std::isfinite(dm) ? dm : 1.0;
+  }
+}
+
+// Fixed-point scale of the symmetric pair sums: |pair sum| <= sum_j |q~_j| / (d_min/ux)^2 =: B
+// for every particle of the sample (each term is at most |q~_j| / d_ij^2), so 2^62 / B (rounded
+// down to a power of two) units per unit of sum cannot overflow 64 bits.
+depo_status upload_fx_scale(depo_ctx *ctx, hipStream_t stream) {
+  if (ctx->fp64() || ctx->S == 0) return DEPO_OK;
+  std::vector<double> sc(ctx->S, 1.0);
+  for (int s = 0; s < ctx->S; ++s) {
+    const double dq = ctx->dmin[s] * ctx->ph.inv_ux;
+    const double bound = std::fabs(ctx->samples[s].charge_scale) * ctx->sum_abs_qb[s] / ctx->ph.q_ref / (dq * dq);
+    if (bound > 0.0 && std::isfinite(bound)) sc[s] = std::ldexp(1.0, 62 - (int)std::ceil(std::log2(bound)));
+  }
+  HIP_TRY(hipMemcpyAsync(ctx->sf.fx_scale, sc.data(), sc.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  return DEPO_OK;
+}
+
 bool short_range_on(const depo_ctx *ctx) { return (ctx->p.flags & (DEPO_COLLIDE | DEPO_VDW)) != 0; }
+
+template <class Real> void enqueue_coulomb(depo_ctx *ctx, hipStream_t s) {
+  if (!(ctx->p.flags & DEPO_COULOMB)) return;
+  if constexpr (std::is_same<Real, float>::value) {
+    if (ctx->ccfg.symmetric) {
+      launch_coulomb_sym(ctx->sf, ctx->ph, ctx->n_diag, ctx->n_off, ctx->ccfg, s);
+      return;
+    }
+  }
+  launch_coulomb<Real>(state<Real>(ctx), ctx->ph, ctx->n_tiles, ctx->ccfg, s);
+}
 
 // Enqueue the force evaluation at the current positions (prepare has run).
 template <class Real> void enqueue_forces(depo_ctx *ctx, hipStream_t s) {
   const State<Real> &st = state<Real>(ctx);
   if (short_range_on(ctx)) launch_cells<Real>(st, ctx->ph, ctx->n_cells, (ctx->n_cells + 1023) / 1024, s);
-  if (ctx->p.flags & DEPO_COULOMB) launch_coulomb<Real>(st, ctx->ph, ctx->n_tiles, ctx->ccfg, s);
+  enqueue_coulomb<Real>(ctx, s);
   if (short_range_on(ctx)) launch_short_range<Real>(st, ctx->ph, ctx->n_cells, s);
 }
 
@@ -274,7 +365,7 @@ template <class Real> depo_status run_steps_timed(depo_ctx *ctx, int n, hipStrea
     HIP_TRY(hipEventRecord(E[1], s));
     if (short_range_on(ctx)) launch_cells<Real>(st, ctx->ph, ctx->n_cells, (ctx->n_cells + 1023) / 1024, s);
     HIP_TRY(hipEventRecord(E[2], s));
-    if (ctx->p.flags & DEPO_COULOMB) launch_coulomb<Real>(st, ctx->ph, ctx->n_tiles, ctx->ccfg, s);
+    enqueue_coulomb<Real>(ctx, s);
     HIP_TRY(hipEventRecord(E[3], s));
     if (short_range_on(ctx)) launch_short_range<Real>(st, ctx->ph, ctx->n_cells, s);
     HIP_TRY(hipEventRecord(E[4], s));
@@ -429,6 +520,15 @@ depo_status do_seed(depo_ctx *ctx, const depo_sample_params *sp, const double *h
   HIP_TRY(hipMemcpyAsync(st.nstep, zero, 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(st.err, zero, 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (!ctx->fp64()) {
+    set_charge_bounds(ctx, hd, hq);
+    depo_status u = upload_fx_scale(ctx, s);
+    if (u == DEPO_OK && ctx->ccfg.symmetric) u = upload_items(ctx);
+    if (u != DEPO_OK) return u;
+    launch_clear_int((int32_t *)ctx->sf.accx, 2 * (size_t)N, s);
+    launch_clear_int((int32_t *)ctx->sf.accy, 2 * (size_t)N, s);
+    launch_clear_int((int32_t *)ctx->sf.accz, 2 * (size_t)N, s);
+  }
   // initial force evaluation at x^0 (and v^0 = u_f(x^0) when no velocity is given)
   launch_prepare<Real>(st, ctx->ph, prepare_mode(ctx) | P_SEED, s);
   enqueue_forces<Real>(ctx, s);
@@ -581,6 +681,12 @@ template <class Real> depo_status do_upload(depo_ctx *ctx, const void *blob, siz
   depo_status r = build_samples(ctx, sp.data(), d.data());
   if (r != DEPO_OK) return r;
   ctx->sp = sp;
+  if (!ctx->fp64()) {
+    std::vector<double> qb(N);
+    std::memcpy(qb.data(), q + N * 8, N * 8);
+    set_charge_bounds(ctx, d.data(), qb.data());
+    if ((r = upload_fx_scale(ctx, s)) != DEPO_OK) return r;
+  }
   auto put = [&](void *dst, size_t n) -> depo_status {
     HIP_TRY(hipMemcpyAsync(dst, p, n, hipMemcpyHostToDevice, s));
     p += n;
@@ -800,6 +906,15 @@ depo_status depo_set_layout(depo_ctx *ctx, int32_t n_samples, const int64_t *off
   int tiles = 0;
   for (int s = 0; s < n_samples; ++s) tiles += (int)((offsets[s + 1] - offsets[s] + 63) / 64);
   ctx->tile_cap = tiles;
+  // symmetric pair kernel (FP32): work items for the smallest item size
+  ctx->sym_cap = 0;
+  if (!ctx->fp64()) {
+    const int64_t T = kSymTileMin;
+    for (int s = 0; s < n_samples; ++s) {
+      const int64_t nt = (offsets[s + 1] - offsets[s] + T - 1) / T;
+      ctx->sym_cap += nt * (nt + 1) / 2;
+    }
+  }
   fill_phys(ctx);
   ctx->ws_need = ctx->fp64() ? carve<double>(ctx, nullptr, ctx->sd) : carve<float>(ctx, nullptr, ctx->sf);
   return DEPO_OK;
@@ -862,6 +977,7 @@ depo_status depo_set_sample_params(depo_ctx *ctx, const depo_sample_params *sp, 
     ctx->samples[k].temperature = sp[k].temperature;
   }
   ctx->sp.assign(sp, sp + ctx->S);
+  if (depo_status u = upload_fx_scale(ctx, (hipStream_t)stream); u != DEPO_OK) return u;
   SampleDev *dst = ctx->fp64() ? ctx->sd.samples : ctx->sf.samples;
   HIP_TRY(hipMemcpyAsync(dst, ctx->samples.data(), ctx->S * sizeof(SampleDev), hipMemcpyHostToDevice,
                          (hipStream_t)stream));
@@ -886,12 +1002,21 @@ depo_status depo_step_timed(depo_ctx *ctx, int32_t n_steps, depo_stream stream, 
 }
 
 depo_status depo_set_kernel_config(depo_ctx *ctx, int32_t targets_per_lane, int32_t waves, int32_t block,
-                                   int32_t compensated, int32_t use_graph) {
+                                   int32_t mode, int32_t use_graph) {
   if (!ctx) return DEPO_E_INVALID;
-  CoulombConfig c{targets_per_lane, waves, block, compensated != 0};
-  if (!coulomb_config_supported(ctx->p.real_bytes, c))
+  if (mode < DEPO_PAIR_PLAIN || mode > DEPO_PAIR_SYMMETRIC)
+    return ctx->fail(DEPO_E_INVALID, "unknown pair-kernel mode %d", mode);
+  CoulombConfig c{targets_per_lane, waves, block, mode != DEPO_PAIR_PLAIN, mode == DEPO_PAIR_SYMMETRIC};
+  if (c.symmetric) {
+    if (ctx->fp64() || !coulomb_sym_supported(c))
+      return ctx->fail(DEPO_E_INVALID, "unsupported symmetric pair-kernel configuration (%d, %d, %d)", targets_per_lane,
+                       waves, block);
+    if (coulomb_sym_tile(c) < kSymTileMin)
+      return ctx->fail(DEPO_E_INVALID, "symmetric items must hold at least %d targets", kSymTileMin);
+  } else if (!coulomb_config_supported(ctx->p.real_bytes, c)) {
     return ctx->fail(DEPO_E_INVALID, "unsupported pair-kernel configuration (%d, %d, %d, %d)", targets_per_lane, waves,
-                     block, compensated);
+                     block, mode);
+  }
   ctx->ccfg = c;
   ctx->use_graph = use_graph != 0;
   ctx->drop_graph();
@@ -901,6 +1026,7 @@ depo_status depo_set_kernel_config(depo_ctx *ctx, int32_t targets_per_lane, int3
     ctx->n_tiles = (int)tiles.size();
     TileDev *dst = ctx->fp64() ? ctx->sd.tiles : ctx->sf.tiles;
     HIP_TRY(hipMemcpy(dst, tiles.data(), tiles.size() * sizeof(TileDev), hipMemcpyHostToDevice));
+    if (c.symmetric) return upload_items(ctx);
   }
   return DEPO_OK;
 }

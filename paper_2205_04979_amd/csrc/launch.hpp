@@ -23,14 +23,22 @@ void launch_clear_int(int32_t *p, size_t n, hipStream_t s);
 // Coulomb pair sums.
 struct CoulombConfig {
   int ipl;     // targets per lane
-  int waves;   // waves per workgroup (split the source range)
+  int waves;   // waves per workgroup (split the source range; symmetric: each owns 64*ipl targets)
   int block;   // sources per compensated block
   bool compensated;  // Kahan accumulation of the block sums (FP32); plain sums otherwise
+  bool symmetric = false;  // FP32: each unordered pair once, reaction on the source (Newton's third law)
 };
 template <class Real>
 void launch_coulomb(const State<Real> &st, const Phys &ph, int n_tiles, const CoulombConfig &cfg, hipStream_t s);
 int coulomb_tile_targets(const CoulombConfig &cfg);
 bool coulomb_config_supported(int real_bytes, const CoulombConfig &cfg);
+
+// Symmetric FP32 pair sums: diagonal items, off-diagonal items, then the fixed-order
+// reduction of each particle's partial slots into cx/cy/cz.
+int coulomb_sym_tile(const CoulombConfig &cfg);   // targets (= sources) per item
+bool coulomb_sym_supported(const CoulombConfig &cfg);
+void launch_coulomb_sym(const State<float> &st, const Phys &ph, int n_diag, int n_off, const CoulombConfig &cfg,
+                        hipStream_t s);
 
 // One-dimensional Eulerian low-fidelity model, one lane per particle class.
 struct LfConst {

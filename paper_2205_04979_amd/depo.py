@@ -27,6 +27,9 @@ FLAG_BITS = {
 PHASES = ("prepare", "cells", "coulomb", "short_range", "finish")
 
 
+PAIR_PLAIN, PAIR_KAHAN, PAIR_SYMMETRIC = 0, 1, 2
+
+
 class DepoError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{msg} (status {status})")
@@ -246,11 +249,14 @@ class Simulation(Context):
         self.check(self._L.depo_set_sample_params(self._h, self._sp_array(sample_params), self._stream(stream)),
                    "depo_set_sample_params")
 
-    def set_kernel_config(self, targets_per_lane: int, waves: int, block: int, compensated: Optional[bool] = None,
-                          use_graph: bool = True):
-        if compensated is None:
-            compensated = self.real_bytes == 4
-        self.check(self._L.depo_set_kernel_config(self._h, targets_per_lane, waves, block, int(compensated),
+    def set_kernel_config(self, targets_per_lane: int, waves: int, block: int, mode=None, use_graph: bool = True,
+                          compensated: Optional[bool] = None):
+        """Pair-kernel shape and mode: PAIR_PLAIN, PAIR_KAHAN or PAIR_SYMMETRIC (FP32); the default is Kahan in
+        FP32 and plain in FP64.  ``compensated`` (bool) is accepted in place of ``mode`` for the one-sided modes."""
+        if mode is None:
+            mode = (PAIR_KAHAN if compensated else PAIR_PLAIN) if compensated is not None else (
+                PAIR_KAHAN if self.real_bytes == 4 else PAIR_PLAIN)
+        self.check(self._L.depo_set_kernel_config(self._h, targets_per_lane, waves, block, int(mode),
                                                   int(use_graph)), "depo_set_kernel_config")
 
     def step(self, n: int = 1, stream=None):

@@ -139,9 +139,17 @@ def test_kernel_config_validation(depo):
     assert L.depo_set_kernel_config(ctx._h, 2, 8, 32, 0, 1) == depo.E_INVALID     # plain sums: one shape only
     assert L.depo_set_kernel_config(ctx._h, 1, 16, 32, 0, 1) == depo.OK
     assert L.depo_set_kernel_config(ctx._h, 1, 16, 64, 1, 0) == depo.OK
+    # symmetric mode (2): FP32 only, items of at least 512 targets, compiled shapes only
+    assert L.depo_set_kernel_config(ctx._h, 1, 8, 64, 2, 1) == depo.OK
+    assert L.depo_set_kernel_config(ctx._h, 4, 2, 64, 2, 1) == depo.OK
+    assert L.depo_set_kernel_config(ctx._h, 1, 2, 64, 2, 1) == depo.E_INVALID      # 128-target items
+    assert L.depo_set_kernel_config(ctx._h, 1, 8, 32, 2, 1) == depo.E_INVALID      # rounds are 64 sources
+    assert L.depo_set_kernel_config(ctx._h, 1, 8, 64, 3, 1) == depo.E_INVALID      # unknown mode
+    assert L.depo_set_kernel_config(ctx._h, 1, 8, 64, -1, 1) == depo.E_INVALID
     ctx64 = depo.Context(physical_params(), 8)
     assert L.depo_set_kernel_config(ctx64._h, 2, 8, 32, 0, 1) == depo.E_INVALID
     assert L.depo_set_kernel_config(ctx64._h, 1, 4, 16, 0, 0) == depo.OK
+    assert L.depo_set_kernel_config(ctx64._h, 1, 8, 64, 2, 1) == depo.E_INVALID
 
 
 def test_adjoint_host_validation(depo):

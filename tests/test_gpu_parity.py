@@ -186,13 +186,18 @@ def test_fp32_plain_1k_200_steps_within_error_bars():
     assert abs(tgp["v_dep"] - to["v_dep"]) <= se + 1e-30
 
 
-def test_fp32_single_65k_sampled_forces():
-    """Full 65,536-particle workload in the launch configuration the benchmark times: force error of
-    sampled targets against the oracle evaluated on the GPU's own snapshot, at seed and after 20 steps."""
+@pytest.mark.parametrize("cfg", [None, (1, 8, 64, 2), (4, 2, 64, 2)])
+def test_fp32_single_65k_sampled_forces(cfg):
+    """Full 65,536-particle workload in the launch configurations the benchmark times (one-sided and
+    symmetric pair kernels): force error of sampled targets against the oracle evaluated on the GPU's
+    own snapshot, at seed and after 20 steps."""
     w = make_workload("single-65k")
     f = w.field()
-    say("case: single-65k fp32 sampled forces")
+    say("case: single-65k fp32 sampled forces", cfg)
     sim, _ = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4, oracle=False)
+    if cfg:
+        sim.set_kernel_config(*cfg)
+        sim.eval_accel()
     rng = np.random.default_rng(0)
     targets = np.sort(rng.choice(w.n_particles, 96, replace=False))
     for steps in (0, 20):
@@ -208,13 +213,18 @@ def test_fp32_single_65k_sampled_forces():
         assert e.max() < 1e-5
 
 
-def test_fp32_bitwise_deterministic_and_checkpoint_roundtrip():
+@pytest.mark.parametrize("cfg", [None, (1, 8, 64, 2)])
+def test_fp32_bitwise_deterministic_and_checkpoint_roundtrip(cfg):
+    """Repeated runs are bitwise equal (the symmetric kernel combines its items with integer atomics,
+    whose order does not matter), and a checkpoint restores the exact trajectory."""
     w = make_workload("single-65k", n=8192, field_n=32)
     f = w.field()
-    say("case: determinism / checkpoint fp32 n=8192")
+    say("case: determinism / checkpoint fp32 n=8192", cfg)
     runs = []
     for _ in range(2):
         sim, _ = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4, oracle=False)
+        if cfg:
+            sim.set_kernel_config(*cfg)
         sim.step(10)
         runs.append(sim.read())
     for k in ("x", "v", "a", "dep_step"):
@@ -255,9 +265,12 @@ def test_graph_replay_equals_direct_launch():
         assert np.array_equal(out[0][k], out[1][k]), k
 
 
-@pytest.mark.parametrize("cfg", [(1, 4, 32), (2, 8, 32), (4, 4, 32), (2, 16, 32), (1, 16, 64), (2, 8, 64)])
+@pytest.mark.parametrize("cfg", [(1, 4, 32), (2, 8, 32), (4, 4, 32), (2, 16, 32), (1, 16, 64), (2, 8, 64),
+                                 (1, 4, 64, 2), (1, 8, 64, 2), (2, 2, 64, 2), (2, 4, 64, 2), (4, 1, 64, 2),
+                                 (4, 2, 64, 2), (4, 4, 64, 2), (8, 1, 64, 2)])
 def test_fp32_kernel_shapes_agree(cfg):
-    """Every compiled pair-kernel shape gives the same forces up to FP32 summation order."""
+    """Every compiled pair-kernel shape, one-sided or symmetric (mode 2: 3,000 particles = 6 items of 512
+    or 3 of 1,024 per side, ragged last tile), gives the oracle's forces up to FP32 summation order."""
     w = make_workload("single-65k", n=3000, field_n=32)
     f = w.field()
     say("case: pair-kernel shape", cfg)
@@ -285,7 +298,7 @@ def test_nonfinite_is_reported():
 
 
 def test_autotune_restores_state_and_picks_a_compiled_shape():
-    from paper_2205_04979_amd.autotune import FP32_SHAPES, autotune
+    from paper_2205_04979_amd.autotune import FP32_SHAPES, FP32_SYM_SHAPES, autotune
     w = make_workload("single-65k", n=4096, field_n=32)
     f = w.field()
     sim, _ = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4, oracle=False)
@@ -293,19 +306,23 @@ def test_autotune_restores_state_and_picks_a_compiled_shape():
     before = sim.read()
     best, times = autotune(sim, steps=2)
     after = sim.read()
-    assert best in FP32_SHAPES and set(times) == set(FP32_SHAPES)
+    assert best in FP32_SHAPES + FP32_SYM_SHAPES and set(times) == set(FP32_SHAPES + FP32_SYM_SHAPES)
     for k in ("x", "v", "a", "dep_step"):
         assert np.array_equal(before[k], after[k]), k
     sim.step(2)            # still steps normally with the chosen shape
 
 
-def test_fp32_batched_samples_sampled_forces():
+@pytest.mark.parametrize("cfg", [None, (1, 8, 64, 2)])
+def test_fp32_batched_samples_sampled_forces(cfg):
     """Many Monte Carlo samples of uneven size in one launch: per-sample force parity on sampled targets
     (sources restricted to the target's own sample), at seed and after 10 steps."""
     w = make_workload("batched-256", n_samples=24, n_lo=512, n_hi=6000, field_n=64)
     f = w.field()
-    say("case: batched fp32, S =", w.n_samples, "N =", w.n_particles)
+    say("case: batched fp32, S =", w.n_samples, "N =", w.n_particles, cfg)
     sim, _ = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4, oracle=False)
+    if cfg:
+        sim.set_kernel_config(*cfg)
+        sim.eval_accel()
     rng = np.random.default_rng(1)
     targets = np.sort(np.concatenate([rng.choice(np.arange(w.offsets[s], w.offsets[s + 1]), 3, replace=False)
                                       for s in range(w.n_samples)]))
@@ -322,6 +339,36 @@ def test_fp32_batched_samples_sampled_forces():
     t = sim.tally()
     assert len(t) == w.n_samples and all(x["n_alive"] + x["n_dep"] == w.offsets[s + 1] - w.offsets[s]
                                          for s, x in enumerate(t))
+
+
+@pytest.mark.parametrize("cfg", [(1, 8, 64, 2), (4, 1, 64, 2), (4, 4, 64, 2)])
+def test_fp32_symmetric_every_particle_of_uneven_samples(cfg):
+    """Symmetric pair sums over samples smaller than one item, of one item and of several with ragged
+    tails: every particle's acceleration at seed against the oracle, and Newton's third law: the
+    charge-weighted Coulomb sums of each sample add up to zero (up to rounding)."""
+    w = make_workload("batched-256", n_samples=6, n_lo=100, n_hi=2200, field_n=32)
+    f = w.field()
+    say("case: symmetric every particle, sizes", np.diff(w.offsets).tolist(), cfg)
+    sim, ora = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4)
+    sim.set_kernel_config(*cfg)
+    sim.eval_accel()
+    g = sim.read()
+    tg = np.arange(w.n_particles)
+    e = force_error(g["a"], ora.a, coulomb_scale(ora, tg))
+    say("force error max", e.max())
+    assert e.max() < 1e-5
+    # with collisions, cohesion, wall terms and drag off, m_i a_i are pairwise equal and opposite
+    p = dict(w.params, drag=False, collide=False, vdw=False, wall_image=False, wall_vdw=False)
+    sim2, _ = seeded_pair(p, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4, oracle=False)
+    sim2.set_kernel_config(*cfg)
+    sim2.eval_accel()
+    a = sim2.read()["a"].astype(np.float64)
+    m = w.params["rho_p"] * np.pi * w.d ** 3 / 6
+    scale = m * coulomb_scale(ora, tg)          # sum_j |F_ij| per particle
+    for s in range(w.n_samples):
+        sl = slice(w.offsets[s], w.offsets[s + 1])
+        F = m[sl, None] * a[sl]
+        assert np.all(np.abs(F.sum(0)) <= 1e-6 * scale[sl].sum()), s
 
 
 def test_fp32_large_1m_force_error_compensated_vs_plain():
