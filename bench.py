@@ -82,22 +82,35 @@ def cpu_baseline(w, field, n_targets: int):
                 seconds=wall)
 
 
-def kernel_source_digest() -> str:
+def kernel_source_digest(name: str) -> str:
     import hashlib
-    src = os.path.join(ROOT, "paper_2205_04979_amd", "csrc", "k_coulomb.hip")
+    src = os.path.join(ROOT, "paper_2205_04979_amd", "csrc", name)
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def pair_kernel_source(shape) -> str:
+    """Source file of the pair kernel a shape selects (4th entry 2: the symmetric kernel)."""
+    return "k_coulomb_sym.hip" if len(shape) > 3 and shape[3] == 2 else "k_coulomb.hip"
+
+
+def pair_kernel_name(shape) -> str:
+    if len(shape) > 3 and shape[3] == 2:
+        return f"k_coulomb_sym<{shape[0]}, {shape[1]}> + k_pair_finish (symmetric direct pair sums)"
+    return f"k_coulomb<float, {shape[0]}, {shape[1]}, {shape[2]}> (one-sided direct pair sums)"
 
 
 def measured_traffic(shape):
     """HBM bytes per pair-kernel launch from the committed counter summary, if it was taken on this
     exact kernel source and shape; otherwise None."""
-    path = os.path.join(ROOT, "profiles", "k_coulomb_single65k_hbm_counters.json")
+    path = os.path.join(ROOT, "profiles", "pair_kernel_single65k_hbm_counters.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path))
-    if rec.get("k_coulomb_sha256_16") != kernel_source_digest() or tuple(rec.get("shape", ())) != tuple(shape):
-        return None
-    return rec.get("bytes_per_launch")
+    src = pair_kernel_source(shape)
+    for rec in json.load(open(path))["records"]:
+        if rec.get("source") == src and rec.get("sha256_16") == kernel_source_digest(src) and \
+                tuple(rec.get("shape", ())) == tuple(shape):
+            return rec.get("bytes_per_launch")
+    return None
 
 
 def batched_run(steps: int) -> dict:
@@ -363,7 +376,7 @@ def main():
     roofline = {
         "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": measured_traffic(shape),
-        "kernel": "k_coulomb (direct pair sums)", "kernel_ms": round(coul_ms, 5),
+        "kernel": pair_kernel_name(shape), "kernel_ms": round(coul_ms, 5),
         "algorithmic": f"{FLOPS_PER_PAIR} flop per unordered pair x N(N-1)/2 pairs per launch",
         "ordered_pairs_per_s": round(2 * pairs / (coul_ms * 1e-3), 1),
         "frac_of_nonpacked_fma_peak": round(achieved / NONPACKED_FMA_TFLOPS, 4),

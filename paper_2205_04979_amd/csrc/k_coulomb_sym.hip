@@ -90,7 +90,7 @@ __device__ __forceinline__ void ring_item(const SymItem &it, const JSrc<float> *
 #pragma unroll
     for (int k = 0; k < IPL; ++k) sx[k] = sy[k] = sz[k] = 0.0f;
     uint64_t nearmask = 0;
-#pragma unroll 8
+#pragma unroll 4
     for (int t = 0; t < 64; ++t) {
       const JSrc<float> s = rs[t];
 #pragma unroll
