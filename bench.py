@@ -339,7 +339,7 @@ def main():
         shape, tune = autotune(sim, steps=3)
         log(f"[bench] autotuned pair kernel: {shape} " + ", ".join(f"{k}:{v:.3f}ms" for k, v in tune.items()))
     else:
-        shape = (1, 8, 32)
+        shape = (4, 2, 64, 2)          # the library default in FP32
     if args.copy_probe_mb:
         src = torch.empty(args.copy_probe_mb << 20, dtype=torch.uint8, device="cuda:0").fill_(1)
         dst = torch.empty_like(src)

@@ -208,10 +208,13 @@ enum {
  * workgroup, sources per block, mode DEPO_PAIR_*) and whether depo_step
  * replays a captured HIP graph (use_graph != 0, the default) or launches
  * kernels directly.  DEPO_E_INVALID for a shape that is not compiled in.
- * Defaults: (1, 8, 32, DEPO_PAIR_KAHAN) in FP32, (1, 4, 16, DEPO_PAIR_PLAIN) in
- * FP64; block 64 selects the one-sided variant that prefetches source records
- * one group ahead.  The symmetric mode takes block = 64 (sources are paired in
- * rounds of 64) and items of 64 * targets_per_lane * waves >= 256 targets. */
+ * Defaults: (4, 2, 64, DEPO_PAIR_SYMMETRIC) in FP32 (or (1, 8, 32,
+ * DEPO_PAIR_KAHAN) for a layout with more than 2^22 symmetric items),
+ * (1, 4, 16, DEPO_PAIR_PLAIN) in FP64; block 64 selects the one-sided variant
+ * that prefetches source records one group ahead.  The symmetric mode takes
+ * block = 64 (sources are paired in rounds of 64) and items of
+ * 64 * targets_per_lane * waves >= 256 targets, at most 2^22 of them per
+ * layout (DEPO_E_INVALID beyond). */
 depo_status depo_set_kernel_config(depo_ctx *ctx, int32_t targets_per_lane, int32_t waves, int32_t block,
                                    int32_t mode, int32_t use_graph);
 

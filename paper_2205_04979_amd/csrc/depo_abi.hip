@@ -18,7 +18,11 @@
 
 using namespace depo;
 
-constexpr int kSymTileMin = 256;   // smallest symmetric pair-kernel item (64 * ipl * waves targets)
+constexpr int kSymTileMin = 256;       // smallest symmetric pair-kernel item (64 * ipl * waves targets)
+constexpr int64_t kMaxItems = 1 << 22; // largest symmetric item list a layout reserves room for (32 B each)
+// FP32 defaults: the symmetric kernel, or the one-sided kernel where the layout has too many items
+const CoulombConfig kDefaultSym{4, 2, 64, true, true};
+const CoulombConfig kDefaultOneSided{1, 8, 32, true};
 
 namespace {
 
@@ -84,7 +88,7 @@ struct depo_ctx {
   std::vector<SampleDev> samples;
   std::vector<depo_sample_params> sp;
   double dmax_all = 0.0;
-  CoulombConfig ccfg{1, 8, 32, true};
+  CoulombConfig ccfg = kDefaultSym;
   Phys ph{};
   State<float> sf{};
   State<double> sd{};
@@ -289,6 +293,16 @@ depo_status upload_fx_scale(depo_ctx *ctx, hipStream_t stream) {
 }
 
 bool short_range_on(const depo_ctx *ctx) { return (ctx->p.flags & (DEPO_COLLIDE | DEPO_VDW)) != 0; }
+
+// Items of the symmetric kernel for item size T: n_t (n_t + 1) / 2 per sample.
+int64_t count_items(const std::vector<int64_t> &off, int64_t T) {
+  int64_t total = 0;
+  for (size_t s = 0; s + 1 < off.size(); ++s) {
+    const int64_t nt = (off[s + 1] - off[s] + T - 1) / T;
+    total += nt * (nt + 1) / 2;
+  }
+  return total;
+}
 
 template <class Real> void enqueue_coulomb(depo_ctx *ctx, hipStream_t s) {
   if (!(ctx->p.flags & DEPO_COULOMB)) return;
@@ -906,14 +920,16 @@ depo_status depo_set_layout(depo_ctx *ctx, int32_t n_samples, const int64_t *off
   int tiles = 0;
   for (int s = 0; s < n_samples; ++s) tiles += (int)((offsets[s + 1] - offsets[s] + 63) / 64);
   ctx->tile_cap = tiles;
-  // symmetric pair kernel (FP32): work items for the smallest item size
+  // symmetric pair kernel (FP32): room for the items of the smallest item size whose list stays
+  // within kMaxItems; the FP32 default falls back to the one-sided kernel beyond that
   ctx->sym_cap = 0;
   if (!ctx->fp64()) {
-    const int64_t T = kSymTileMin;
-    for (int s = 0; s < n_samples; ++s) {
-      const int64_t nt = (offsets[s + 1] - offsets[s] + T - 1) / T;
-      ctx->sym_cap += nt * (nt + 1) / 2;
+    for (int64_t T = kSymTileMin; T <= 1024 && ctx->sym_cap == 0; T *= 2) {
+      const int64_t k = count_items(ctx->off, T);
+      if (k <= kMaxItems) ctx->sym_cap = k;
     }
+    if (ctx->ccfg.symmetric && count_items(ctx->off, coulomb_sym_tile(ctx->ccfg)) > ctx->sym_cap)
+      ctx->ccfg = kDefaultOneSided;
   }
   fill_phys(ctx);
   ctx->ws_need = ctx->fp64() ? carve<double>(ctx, nullptr, ctx->sd) : carve<float>(ctx, nullptr, ctx->sf);
@@ -1013,6 +1029,8 @@ depo_status depo_set_kernel_config(depo_ctx *ctx, int32_t targets_per_lane, int3
                        waves, block);
     if (coulomb_sym_tile(c) < kSymTileMin)
       return ctx->fail(DEPO_E_INVALID, "symmetric items must hold at least %d targets", kSymTileMin);
+    if (ctx->has_layout && count_items(ctx->off, coulomb_sym_tile(c)) > ctx->sym_cap)
+      return ctx->fail(DEPO_E_INVALID, "too many symmetric work items for this layout; use larger items");
   } else if (!coulomb_config_supported(ctx->p.real_bytes, c)) {
     return ctx->fail(DEPO_E_INVALID, "unsupported pair-kernel configuration (%d, %d, %d, %d)", targets_per_lane, waves,
                      block, mode);
