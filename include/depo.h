@@ -199,9 +199,10 @@ depo_status depo_step_timed(depo_ctx *ctx, int32_t n_steps, depo_stream stream, 
 enum {
   DEPO_PAIR_PLAIN = 0,      /* one-sided sums, plain accumulation                          */
   DEPO_PAIR_KAHAN = 1,      /* one-sided sums, Kahan-compensated block accumulation        */
-  DEPO_PAIR_SYMMETRIC = 2   /* FP32 only: every unordered pair once, the reaction applied to
+  DEPO_PAIR_SYMMETRIC = 2,  /* FP32 only: every unordered pair once, the reaction applied to
                              * the source (Newton's third law); Kahan on the target side,
-                             * FP64 combination of per-tile partials                        */
+                             * 64-bit fixed-point combination of per-item partials          */
+  DEPO_PAIR_P3M = 3         /* P3M electrostatics (configured with depo_set_p3m)           */
 };
 
 /* Choose the Coulomb pair-kernel shape (targets per lane, wavefronts per
@@ -217,6 +218,24 @@ enum {
  * layout (DEPO_E_INVALID beyond). */
 depo_status depo_set_kernel_config(depo_ctx *ctx, int32_t targets_per_lane, int32_t waves, int32_t block,
                                    int32_t mode, int32_t use_graph);
+
+/* P3M electrostatics (Appendix A.2.4, Eq. coulomb_force): the Coulomb sums
+ * from a Gaussian split into a short-range direct part and a long-range mesh
+ * part solved with FFTs, O(N log N).  It computes the lattice sum over all x
+ * images (period L) with free space across the pipe section, not the nearest
+ * image of the direct modes.  Mesh: mesh_x nodes along x (power of two,
+ * 16..1024) and mesh_yz across [-R, R] (power of two, 16..512, with one spare
+ * node on each side), zero-padded to 2 mesh_yz; splitting parameter
+ * alpha = alpha_h / h (h the larger spacing, 0 < alpha_h <= 2) and short-range
+ * cutoff r_max = rmax_alpha / alpha (2 <= rmax_alpha <= 6).  Triangular-
+ * shaped-cloud assignment and interpolation, image-summed Green's function
+ * deconvolved by the squared TSC transfer, FP64 mesh and FFTs, deterministic.
+ * Must be called before depo_set_layout (it sizes the workspace: about
+ * 80 B per mesh node); needs a single-sample layout with L >= 3 r_max, and
+ * selects P3M as the Coulomb solver (depo_set_kernel_config switches between
+ * it, mode DEPO_PAIR_P3M, and the direct modes).  The adjoint rejects P3M.
+ * DEPO_E_STATE after the layout is set, DEPO_E_INVALID for bad sizes. */
+depo_status depo_set_p3m(depo_ctx *ctx, int32_t mesh_x, int32_t mesh_yz, double alpha_h, double rmax_alpha);
 
 /* Recompute the non-drag acceleration of every alive particle at the
  * current positions and velocities (the force evaluation of a step without

@@ -19,6 +19,7 @@
 using namespace depo;
 
 constexpr int kSymTileMin = 256;       // smallest symmetric pair-kernel item (64 * ipl * waves targets)
+constexpr int kP3mImages = 256;        // x images summed into the P3M Green's function
 constexpr int64_t kMaxItems = 1 << 22; // largest symmetric item list a layout reserves room for (32 B each)
 // FP32 defaults: the symmetric kernel, or the one-sided kernel where the layout has too many items
 const CoulombConfig kDefaultSym{4, 2, 64, true, true};
@@ -76,6 +77,12 @@ struct depo_ctx {
   // item counts, per-sample bounds for the fixed-point scale
   int64_t sym_cap = 0;
   int n_diag = 0, n_off = 0;
+  // P3M electrostatics (configured before the layout; single-sample layouts)
+  bool p3m_cfg = false, p3m_use = false, p3m_green = false;
+  int p3m_nx = 0, p3m_nc = 0;
+  double p3m_alpha_h = 0.0, p3m_rmax_alpha = 0.0;
+  P3mDev pm{};
+  double *p3m_qscale = nullptr;
   std::vector<double> sum_abs_qb, dmin;
   // workspace
   size_t ws_need = 0;
@@ -160,6 +167,22 @@ size_t carve(depo_ctx *ctx, char *base, State<Real> &st) {
   st.accx = (unsigned long long *)take(nacc * 8);
   st.accy = (unsigned long long *)take(nacc * 8);
   st.accz = (unsigned long long *)take(nacc * 8);
+  if (ctx->p3m_cfg) {
+    P3mDev &m = ctx->pm;
+    const size_t total = (size_t)m.nx * m.P * m.P, ncell = (size_t)m.ncx * m.ncy * m.ncy;
+    for (int c = 0; c < 3; ++c) m.ghat[c] = (double2 *)take(total * sizeof(double2));
+    m.rho = (double2 *)take(total * sizeof(double2));
+    m.work = (double2 *)take(total * sizeof(double2));
+    m.qmesh = (unsigned long long *)take((size_t)m.nx * m.nc * m.nc * 8);
+    m.slong = (double *)take(3 * N * sizeof(double));
+    m.cell_of = (int32_t *)take(N * 4);
+    m.counts = (int32_t *)take(ncell * 4);
+    m.starts = (int32_t *)take((ncell + 1) * 4);
+    m.fill = (int32_t *)take(ncell * 4);
+    m.sorted = (int32_t *)take(N * 4);
+    ctx->p3m_qscale = (double *)take(64);
+    m.q_scale = ctx->p3m_qscale;
+  }
   st.field = (typename Prec<Real>::Vec4 *)take((size_t)ctx->nx * ctx->ny * ctx->nz * sizeof(typename Prec<Real>::Vec4));
   st.nstep = (int32_t *)take(64);
   st.err = (uint32_t *)take(64);
@@ -276,6 +299,17 @@ void set_charge_bounds(depo_ctx *ctx, const double *h_d, const double *h_qb) {
   }
 }
 
+// Fixed-point scale of the P3M charge mesh: every node holds at most sum_j |q~_j|.
+depo_status upload_p3m_scale(depo_ctx *ctx, hipStream_t stream) {
+  if (!ctx->p3m_cfg || ctx->S == 0) return DEPO_OK;
+  const double bound = std::fabs(ctx->samples[0].charge_scale) * ctx->sum_abs_qb[0] / ctx->ph.q_ref;
+  double sc = 1.0;
+  if (bound > 0.0 && std::isfinite(bound)) sc = std::ldexp(1.0, 62 - (int)std::ceil(std::log2(bound)));
+  HIP_TRY(hipMemcpyAsync(ctx->p3m_qscale, &sc, sizeof sc, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  return DEPO_OK;
+}
+
 // Fixed-point scale of the symmetric pair sums: |pair sum| <= sum_j |q~_j| / (d_min/ux)^2 =: B
 // for every particle of the sample (each term is at most |q~_j| / d_ij^2), so 2^62 / B (rounded
 // down to a power of two) units per unit of sum cannot overflow 64 bits.
@@ -306,6 +340,10 @@ int64_t count_items(const std::vector<int64_t> &off, int64_t T) {
 
 template <class Real> void enqueue_coulomb(depo_ctx *ctx, hipStream_t s) {
   if (!(ctx->p.flags & DEPO_COULOMB)) return;
+  if (ctx->p3m_use) {
+    launch_p3m<Real>(state<Real>(ctx), ctx->ph, ctx->pm, s);
+    return;
+  }
   if constexpr (std::is_same<Real, float>::value) {
     if (ctx->ccfg.symmetric) {
       launch_coulomb_sym(ctx->sf, ctx->ph, ctx->n_diag, ctx->n_off, ctx->ccfg, s);
@@ -534,14 +572,25 @@ depo_status do_seed(depo_ctx *ctx, const depo_sample_params *sp, const double *h
   HIP_TRY(hipMemcpyAsync(st.nstep, zero, 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(st.err, zero, 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
+  set_charge_bounds(ctx, hd, hq);
   if (!ctx->fp64()) {
-    set_charge_bounds(ctx, hd, hq);
     depo_status u = upload_fx_scale(ctx, s);
     if (u == DEPO_OK && ctx->ccfg.symmetric) u = upload_items(ctx);
     if (u != DEPO_OK) return u;
     launch_clear_int((int32_t *)ctx->sf.accx, 2 * (size_t)N, s);
     launch_clear_int((int32_t *)ctx->sf.accy, 2 * (size_t)N, s);
     launch_clear_int((int32_t *)ctx->sf.accz, 2 * (size_t)N, s);
+  }
+  if (ctx->p3m_cfg) {
+    if (depo_status u = upload_p3m_scale(ctx, s); u != DEPO_OK) return u;
+    const P3mDev &m = ctx->pm;
+    launch_clear_int((int32_t *)m.qmesh, 2 * (size_t)m.nx * m.nc * m.nc, s);
+    launch_clear_int(m.counts, (size_t)m.ncx * m.ncy * m.ncy, s);
+    if (!ctx->p3m_green) {
+      p3m_setup_green(m, ctx->p.L, kP3mImages, s);
+      ctx->p3m_green = true;
+    }
+    HIP_TRY(hipGetLastError());
   }
   // initial force evaluation at x^0 (and v^0 = u_f(x^0) when no velocity is given)
   launch_prepare<Real>(st, ctx->ph, prepare_mode(ctx) | P_SEED, s);
@@ -700,6 +749,12 @@ template <class Real> depo_status do_upload(depo_ctx *ctx, const void *blob, siz
     std::memcpy(qb.data(), q + N * 8, N * 8);
     set_charge_bounds(ctx, d.data(), qb.data());
     if ((r = upload_fx_scale(ctx, s)) != DEPO_OK) return r;
+  }
+  if (ctx->p3m_cfg) {
+    std::vector<double> qb(N);
+    std::memcpy(qb.data(), q + N * 8, N * 8);
+    set_charge_bounds(ctx, d.data(), qb.data());
+    if ((r = upload_p3m_scale(ctx, s)) != DEPO_OK) return r;
   }
   auto put = [&](void *dst, size_t n) -> depo_status {
     HIP_TRY(hipMemcpyAsync(dst, p, n, hipMemcpyHostToDevice, s));
@@ -931,6 +986,28 @@ depo_status depo_set_layout(depo_ctx *ctx, int32_t n_samples, const int64_t *off
     if (ctx->ccfg.symmetric && count_items(ctx->off, coulomb_sym_tile(ctx->ccfg)) > ctx->sym_cap)
       ctx->ccfg = kDefaultOneSided;
   }
+  if (ctx->p3m_cfg) {
+    if (n_samples != 1) {
+      ctx->has_layout = false;
+      return ctx->fail(DEPO_E_INVALID, "P3M electrostatics needs a single-sample layout");
+    }
+    P3mDev &m = ctx->pm;
+    m = P3mDev{};
+    m.nx = ctx->p3m_nx;
+    m.nc = ctx->p3m_nc;
+    m.P = 2 * m.nc;
+    m.hx = ctx->p.L / m.nx;
+    m.hy = 2.0 * ctx->p.R / (m.nc - 3);
+    m.alpha = ctx->p3m_alpha_h / std::max(m.hx, m.hy);
+    m.rmax = ctx->p3m_rmax_alpha / m.alpha;
+    m.ncx = (int)std::floor(ctx->p.L / m.rmax);
+    m.ncy = std::max(1, (int)std::floor(2.0 * ctx->p.R / m.rmax));
+    if (m.ncx < 3 || (int64_t)m.ncx * m.ncy * m.ncy > (1 << 22)) {
+      ctx->has_layout = false;
+      return ctx->fail(DEPO_E_INVALID, "P3M cutoff %g m: need L >= 3 r_max and at most 2^22 short-range cells", m.rmax);
+    }
+    ctx->p3m_green = false;
+  }
   fill_phys(ctx);
   ctx->ws_need = ctx->fp64() ? carve<double>(ctx, nullptr, ctx->sd) : carve<float>(ctx, nullptr, ctx->sf);
   return DEPO_OK;
@@ -951,6 +1028,7 @@ depo_status depo_bind(depo_ctx *ctx, void *d_work, size_t bytes) {
   ctx->drop_graph();
   ctx->ws = (char *)d_work;
   if (ctx->fp64()) carve<double>(ctx, ctx->ws, ctx->sd); else carve<float>(ctx, ctx->ws, ctx->sf);
+  ctx->p3m_green = false;
   int32_t *counts = ctx->fp64() ? ctx->sd.cell_count : ctx->sf.cell_count;
   launch_clear_int(counts, (size_t)ctx->cell_cap, nullptr);
   HIP_TRY(hipGetLastError());
@@ -994,6 +1072,7 @@ depo_status depo_set_sample_params(depo_ctx *ctx, const depo_sample_params *sp, 
   }
   ctx->sp.assign(sp, sp + ctx->S);
   if (depo_status u = upload_fx_scale(ctx, (hipStream_t)stream); u != DEPO_OK) return u;
+  if (depo_status u = upload_p3m_scale(ctx, (hipStream_t)stream); u != DEPO_OK) return u;
   SampleDev *dst = ctx->fp64() ? ctx->sd.samples : ctx->sf.samples;
   HIP_TRY(hipMemcpyAsync(dst, ctx->samples.data(), ctx->S * sizeof(SampleDev), hipMemcpyHostToDevice,
                          (hipStream_t)stream));
@@ -1020,6 +1099,13 @@ depo_status depo_step_timed(depo_ctx *ctx, int32_t n_steps, depo_stream stream, 
 depo_status depo_set_kernel_config(depo_ctx *ctx, int32_t targets_per_lane, int32_t waves, int32_t block,
                                    int32_t mode, int32_t use_graph) {
   if (!ctx) return DEPO_E_INVALID;
+  if (mode == DEPO_PAIR_P3M) {
+    if (!ctx->p3m_cfg) return ctx->fail(DEPO_E_INVALID, "P3M is not configured (depo_set_p3m before the layout)");
+    ctx->p3m_use = true;
+    ctx->use_graph = use_graph != 0;
+    ctx->drop_graph();
+    return DEPO_OK;
+  }
   if (mode < DEPO_PAIR_PLAIN || mode > DEPO_PAIR_SYMMETRIC)
     return ctx->fail(DEPO_E_INVALID, "unknown pair-kernel mode %d", mode);
   CoulombConfig c{targets_per_lane, waves, block, mode != DEPO_PAIR_PLAIN, mode == DEPO_PAIR_SYMMETRIC};
@@ -1036,6 +1122,7 @@ depo_status depo_set_kernel_config(depo_ctx *ctx, int32_t targets_per_lane, int3
                      block, mode);
   }
   ctx->ccfg = c;
+  ctx->p3m_use = false;
   ctx->use_graph = use_graph != 0;
   ctx->drop_graph();
   if (ctx->seeded) {
@@ -1122,12 +1209,31 @@ depo_status depo_adjoint(depo_ctx *ctx, int32_t n_steps, int32_t ckpt_every, con
   if (!ctx->seeded) return ctx->fail(DEPO_E_STATE, "seed first");
   if (ctx->nstep != 0) return ctx->fail(DEPO_E_STATE, "the adjoint starts from the seeded state (step 0)");
   if (!(ctx->p.flags & DEPO_SOFT_TALLY)) return ctx->fail(DEPO_E_INVALID, "the adjoint needs DEPO_SOFT_TALLY");
+  if (ctx->p3m_use) return ctx->fail(DEPO_E_INVALID, "the adjoint differentiates the direct Coulomb sum; select a direct mode");
   if (n_steps < 1 || ckpt_every < 1 || ckpt_every > n_steps) return ctx->fail(DEPO_E_INVALID, "need 1 <= ckpt_every <= n_steps");
   if (!h_weights || !h_grad) return ctx->fail(DEPO_E_INVALID, "null weights or gradient array");
   for (int k = 0; k < ctx->S; ++k)
     if (!std::isfinite(h_weights[k])) return ctx->fail(DEPO_E_INVALID, "weight %d not finite", k);
   if (!d_adj_work || ((uintptr_t)d_adj_work % kAlign) != 0) return ctx->fail(DEPO_E_INVALID, "adjoint workspace must be 256-byte aligned");
   return DISPATCH(do_adjoint, ctx, n_steps, ckpt_every, h_weights, h_grad, d_adj_work, bytes, (hipStream_t)stream);
+}
+
+static bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+depo_status depo_set_p3m(depo_ctx *ctx, int32_t mesh_x, int32_t mesh_yz, double alpha_h, double rmax_alpha) {
+  if (!ctx) return DEPO_E_INVALID;
+  if (ctx->has_layout) return ctx->fail(DEPO_E_STATE, "configure P3M before depo_set_layout");
+  if (!pow2_in(mesh_x, 16, 1024) || !pow2_in(mesh_yz, 16, 512) || !(alpha_h > 0.0 && alpha_h <= 2.0) ||
+      !(rmax_alpha >= 2.0 && rmax_alpha <= 6.0))
+    return ctx->fail(DEPO_E_INVALID, "P3M needs power-of-two meshes (16..1024 along x, 16..512 across), "
+                                     "0 < alpha h <= 2 and 2 <= alpha r_max <= 6");
+  ctx->p3m_cfg = true;
+  ctx->p3m_use = true;
+  ctx->p3m_nx = mesh_x;
+  ctx->p3m_nc = mesh_yz;
+  ctx->p3m_alpha_h = alpha_h;
+  ctx->p3m_rmax_alpha = rmax_alpha;
+  return DEPO_OK;
 }
 
 depo_status depo_lf_solve(const depo_params *p, int64_t n, const double *d_diam, const double *d_charge,

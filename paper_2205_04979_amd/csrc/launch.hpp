@@ -40,6 +40,22 @@ bool coulomb_sym_supported(const CoulombConfig &cfg);
 void launch_coulomb_sym(const State<float> &st, const Phys &ph, int n_diag, int n_off, const CoulombConfig &cfg,
                         hipStream_t s);
 
+// P3M electrostatics (single-sample layouts): mesh geometry, splitting and workspace.
+struct P3mDev {
+  int nx, nc, P;          // mesh nodes along x; across the section (with spares); padded P = 2 nc
+  int ncx, ncy;           // short-range cells along x and across the section (cells >= r_max)
+  double hx, hy;          // mesh spacings [m]
+  double alpha, rmax;     // splitting parameter [1/m] and short-range cutoff [m]
+  const double *q_scale;  // device: fixed-point units per unit of scaled charge
+  double2 *ghat[3];       // transformed, deconvolved Green's function per field component
+  double2 *rho, *work;    // transformed charge; one field component
+  unsigned long long *qmesh;   // fixed-point TSC charge, nx x nc x nc (zero between steps)
+  double *slong;          // [3][N] long-range part at the particles [1/m^2]
+  int32_t *cell_of, *counts, *starts, *fill, *sorted;   // short-range cell list
+};
+void p3m_setup_green(const P3mDev &m, double L, int images, hipStream_t s);
+template <class Real> void launch_p3m(const State<Real> &st, const Phys &ph, const P3mDev &m, hipStream_t s);
+
 // One-dimensional Eulerian low-fidelity model, one lane per particle class.
 struct LfConst {
   double R, nu, rho_f, rho_p, re_tau, eps0;

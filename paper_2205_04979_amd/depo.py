@@ -27,7 +27,7 @@ FLAG_BITS = {
 PHASES = ("prepare", "cells", "coulomb", "short_range", "finish")
 
 
-PAIR_PLAIN, PAIR_KAHAN, PAIR_SYMMETRIC = 0, 1, 2
+PAIR_PLAIN, PAIR_KAHAN, PAIR_SYMMETRIC, PAIR_P3M = 0, 1, 2, 3
 
 
 class DepoError(RuntimeError):
@@ -87,6 +87,7 @@ _SIGS = {
     "depo_state_upload": (C.c_int, [_P, _P, C.c_size_t, _P]),
     "depo_adjoint_workspace_bytes": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
     "depo_adjoint": (C.c_int, [_P, C.c_int32, C.c_int32, _DP, _DP, _P, C.c_size_t, _P]),
+    "depo_set_p3m": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_double, C.c_double]),
     "depo_lf_solve": (C.c_int, [C.POINTER(Params), C.c_int64, _P, _P, _P, C.c_int32, C.c_int32, _P, _P]),
 }
 
@@ -199,10 +200,15 @@ class Context:
 class Simulation(Context):
     """One simulation (one or more Monte Carlo samples sharing a field) on a GPU."""
 
-    def __init__(self, params: dict, offsets, field_shape, real_bytes: int = 4, device: str = "cuda:0"):
+    def __init__(self, params: dict, offsets, field_shape, real_bytes: int = 4, device: str = "cuda:0",
+                 p3m: Optional[dict] = None):
+        """``p3m``: P3M electrostatics instead of the direct sums, dict(mesh_x, mesh_yz, alpha_h, rmax_alpha)."""
         import torch
         super().__init__(params, real_bytes)
         self.real_bytes = real_bytes
+        if p3m is not None:
+            self.check(self._L.depo_set_p3m(self._h, int(p3m["mesh_x"]), int(p3m["mesh_yz"]), float(p3m["alpha_h"]),
+                                            float(p3m["rmax_alpha"])), "depo_set_p3m")
         self.device = torch.device(device)
         nx, ny, nz = (int(v) for v in field_shape)
         self.set_layout(offsets, nx, ny, nz)

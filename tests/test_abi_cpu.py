@@ -25,7 +25,7 @@ def depo():
 
 def declared_entry_points():
     src = open(os.path.join(ROOT, "include", "depo.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:depo_status|void|const char \*)\s*(depo_[a-z_]+)\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:depo_status|void|const char \*)\s*(depo_[a-z0-9_]+)\(", src, re.M)))
 
 
 def test_every_declared_symbol_is_exported(depo):
@@ -187,3 +187,26 @@ def test_lf_solve_host_validation(depo):
     for key, value in (("nu", 0.0), ("re_tau", float("nan")), ("eps0", -1.0)):
         bad = depo.make_params(dict(physical_params(), **{key: value}))
         assert L.depo_lf_solve(C.byref(bad), 4, fake, fake, fake, 800, 800, fake, None) == depo.E_INVALID
+
+
+def test_p3m_configuration_validation(depo):
+    """P3M is configured before the layout, with power-of-two meshes and bounded splitting; it needs a
+    single-sample layout whose length holds three cutoff cells."""
+    L = depo.lib()
+    ctx = depo.Context(physical_params(), 4)
+    assert L.depo_set_kernel_config(ctx._h, 1, 8, 64, 3, 1) == depo.E_INVALID           # not configured
+    for args in ((48, 32, 0.5, 3.5), (64, 8, 0.5, 3.5), (64, 32, 0.0, 3.5), (64, 32, 0.5, 1.0), (2048, 32, 0.5, 3.5)):
+        assert L.depo_set_p3m(ctx._h, *args) == depo.E_INVALID, args
+    assert L.depo_set_p3m(ctx._h, 64, 32, 0.5, 3.5) == depo.OK
+    with pytest.raises(depo.DepoError):
+        ctx.set_layout([0, 100, 200], 16, 16, 16)                                           # two samples
+    ctx.set_layout([0, 1000], 16, 16, 16)
+    assert L.depo_set_p3m(ctx._h, 64, 32, 0.5, 3.5) == depo.E_STATE                      # after the layout
+    assert L.depo_set_kernel_config(ctx._h, 1, 8, 64, 3, 1) == depo.OK
+    small = depo.Context(physical_params(), 4)
+    small.set_layout([0, 1000], 16, 16, 16)
+    assert ctx.workspace_bytes() > small.workspace_bytes() + 64 * 64 * 64 * 16 * 5        # five complex meshes
+    coarse = depo.Context(physical_params(), 4)
+    assert L.depo_set_p3m(coarse._h, 16, 16, 0.3, 6.0) == depo.OK                        # r_max > L / 3
+    with pytest.raises(depo.DepoError):
+        coarse.set_layout([0, 1000], 16, 16, 16)

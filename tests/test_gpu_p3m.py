@@ -1,0 +1,121 @@
+"""P3M electrostatics on the GPU (Appendix A.2.4, Eq. coulomb_force) against the P3M oracle (same
+algorithm, FP64) and against the exact x-periodic lattice sum it approximates."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import p3m as op3m
+from oracle.physics import coulomb_constant, particle_mass
+from synthetic import make_workload
+from synthetic.workloads import physical_params
+
+pytestmark = pytest.mark.gpu
+
+COULOMB_ONLY = dict(drag=False, collide=False, vdw=False, wall_image=False, wall_vdw=False)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_accel(w, f, real_bytes, cfg, steps=0, offsets=None):
+    from paper_2205_04979_amd.depo import Simulation
+    sim = Simulation(w.params, w.offsets if offsets is None else offsets, f.shape[:3], real_bytes=real_bytes,
+                     p3m=cfg)
+    sim.init_field(f)
+    sim.seed(w.sample_params, w.x, w.d, w.qbase)
+    if steps:
+        sim.step(steps)
+        sim.eval_accel()
+    return sim, sim.read()
+
+
+def accel_from_sums(p, sp, qbase, d, S):
+    """a_i = k_e q_i S_i / m_i with S in C / m^2."""
+    q = sp[0, 0] * qbase
+    return coulomb_constant(p["eps0"]) * (q / particle_mass(d, p["rho_p"]))[:, None] * S
+
+
+def rel_rms(a, ref):
+    return np.sqrt(np.mean(np.sum((a - ref) ** 2, 1)) / np.mean(np.sum(ref ** 2, 1)))
+
+
+@pytest.mark.parametrize("real_bytes", [8, 4])
+def test_p3m_matches_oracle_p3m(real_bytes):
+    """Same algorithm, same inputs (the GPU's own fixed-point positions): FP64 mesh pipeline agrees with
+    the FP64 oracle to rounding; the FP32 form adds only its FP32 scaled charges and result."""
+    w = make_workload("single-65k", n=600, field_n=16, **COULOMB_ONLY)
+    f = w.field()
+    cfg = dict(mesh_x=32, mesh_yz=16, alpha_h=0.5, rmax_alpha=3.5)
+    say("case: p3m vs oracle p3m, n=600, fp", 8 * real_bytes)
+    sim, g = gpu_accel(w, f, real_bytes, cfg)
+    mesh = op3m.Mesh(w.params["R"], w.params["L"], 32, 16, 0.5, 3.5)
+    q = w.sample_params[0, 0] * w.qbase
+    S = op3m.p3m_sums(mesh, g["x"], q, w.d)
+    a_ora = accel_from_sums(w.params, w.sample_params, w.qbase, w.d, S)
+    err = rel_rms(g["a"], a_ora)
+    say("rel rms vs oracle p3m", err)
+    assert err < (1e-9 if real_bytes == 8 else 2e-6)
+
+
+def test_p3m_close_to_the_lattice_sum_and_deterministic():
+    """Against the exact lattice sum (brute force over 100 x images; the tail beyond is ~1e-8 of the
+    field): relative RMS error at the level of the oracle's pinned P3M accuracy; repeated runs are
+    bitwise equal."""
+    w = make_workload("single-65k", n=1000, field_n=16, **COULOMB_ONLY)
+    f = w.field()
+    cfg = dict(mesh_x=64, mesh_yz=32, alpha_h=0.4, rmax_alpha=3.5)
+    say("case: p3m vs lattice sum, n=1000")
+    _, g = gpu_accel(w, f, 4, cfg)
+    _, g2 = gpu_accel(w, f, 4, cfg)
+    assert np.array_equal(g["a"], g2["a"])
+    q = w.sample_params[0, 0] * w.qbase
+    S = op3m.lattice_sum(g["x"], q, w.d, w.params["L"], images=100)
+    a_ref = accel_from_sums(w.params, w.sample_params, w.qbase, w.d, S)
+    err = rel_rms(g["a"], a_ref)
+    say("rel rms vs lattice sum", err)
+    assert err < 3e-3
+
+
+def test_p3m_single_65k_sampled_against_lattice_sum_and_steps():
+    """The 65,536-particle workload with P3M (mesh 128 x 64, alpha h 0.5): sampled targets against the
+    lattice sum over all sources, at seed and after 10 steps of the full step with every force on."""
+    w = make_workload("single-65k")
+    f = w.field()
+    cfg = dict(mesh_x=128, mesh_yz=64, alpha_h=0.5, rmax_alpha=3.5)
+    say("case: p3m single-65k")
+    pc = dict(w.params, **COULOMB_ONLY)
+    from paper_2205_04979_amd.depo import Simulation
+    sim = Simulation(pc, w.offsets, f.shape[:3], real_bytes=4, p3m=cfg)
+    sim.init_field(f)
+    sim.seed(w.sample_params, w.x, w.d, w.qbase)
+    g = sim.read()
+    rng = np.random.default_rng(3)
+    tg = np.sort(rng.choice(w.n_particles, 24, replace=False))
+    q = w.sample_params[0, 0] * w.qbase
+    L = w.params["L"]
+    S = np.zeros((tg.size, 3))
+    for k, i in enumerate(tg):
+        r = g["x"][i] - g["x"]
+        r[:, 0] -= L * np.round(r[:, 0] / L)
+        m = np.arange(w.n_particles) != i
+        for n in range(-100, 101):
+            rn = r[m] + np.array([n * L, 0.0, 0.0])
+            r2 = np.sum(rn * rn, 1)
+            dij = 0.5 * (w.d[i] + w.d[m])
+            rc2 = np.maximum(r2, dij * dij) if n == 0 else r2
+            S[k] += ((q[m] / (np.sqrt(r2) * rc2))[:, None] * rn).sum(0)
+    a_ref = accel_from_sums(w.params, w.sample_params, w.qbase[tg], w.d[tg], S)
+    err = rel_rms(g["a"][tg], a_ref)
+    say("single-65k sampled rel rms vs lattice sum", err)
+    assert err < 5e-3
+    sim.close()
+    sim2 = Simulation(w.params, w.offsets, f.shape[:3], real_bytes=4, p3m=cfg)
+    sim2.init_field(f)
+    sim2.seed(w.sample_params, w.x, w.d, w.qbase)
+    sim2.step(10)
+    t = sim2.tally()[0]
+    assert t["n_alive"] + t["n_dep"] == w.n_particles and np.all(np.isfinite(sim2.read()["a"]))
