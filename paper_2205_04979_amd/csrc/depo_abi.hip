@@ -180,6 +180,8 @@ size_t carve(depo_ctx *ctx, char *base, State<Real> &st) {
     m.starts = (int32_t *)take((ncell + 1) * 4);
     m.fill = (int32_t *)take(ncell * 4);
     m.sorted = (int32_t *)take(N * 4);
+    m.rec = take(N * 5 * sizeof(typename Prec<Real>::Pos));
+    m.table = (float2 *)take(4096 * sizeof(float2));
     ctx->p3m_qscale = (double *)take(64);
     m.q_scale = ctx->p3m_qscale;
   }

@@ -300,53 +300,161 @@ __global__ void k_p3m_sort(int32_t ncell, const int32_t *__restrict__ starts, in
   counts[c] = 0;
 }
 
-// Short range (Coulomb with the overlap clamp minus the erf field) over nearest-image neighbours
-// closer than r_max, added to the long-range part; result in units of the x quantum.
+// Source record of the short-range pass, in cell-sorted order.
+template <class Real> struct __align__(sizeof(typename Prec<Real>::Pos) == 4 ? 4 : 8) SrRec {
+  typename Prec<Real>::Pos x, y, z;
+  Real q, d;
+};
+
+// Cell-sorted copy of the records the short-range pass reads (contiguous per cell).
 template <class Real>
-__global__ void k_p3m_short(State<Real> st, Phys ph, P3mDev m, const int32_t *__restrict__ starts,
-                            const int32_t *__restrict__ sorted, const double *__restrict__ slong) {
+__global__ void k_p3m_records(State<Real> st, Phys ph, const int32_t *__restrict__ sorted, SrRec<Real> *rec) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ph.N) return;
+  const int i = sorted[k];
+  SrRec<Real> r;
+  r.x = st.px[i];
+  r.y = st.py[i];
+  r.z = st.pz[i];
+  r.q = st.js[i].q;
+  r.d = Real(st.d[i]);
+  rec[k] = r;
+}
+
+constexpr int kSrLds = 65536;    // bytes of LDS for staged neighbour records
+constexpr int kSrWaves = 4;      // waves per cell: each takes every 4th staged source
+constexpr int kSrTable = 4096;   // intervals of the tabulated short-range profile (FP32 form)
+
+// Short-range force profile g(s) = erfc(s) + (2 s / sqrt(pi)) exp(-s^2), s = alpha r, so that the
+// short-range force of a non-overlapping pair is q g(alpha r) r_vec / r^3; tabulated on
+// [0, alpha r_max] as (value, slope) pairs for linear interpolation (interpolation error below
+// 1e-7 of the pair force: |g''| < 1.2 and the step is alpha r_max / 4096).
+__global__ void k_p3m_table(P3mDev m, float2 *__restrict__ tab) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= kSrTable) return;
+  const double hs = m.alpha * m.rmax / kSrTable;
+  auto g = [](double x) { return erfc(x) + 2.0 / sqrt(M_PI) * x * exp(-x * x); };
+  const double s0 = k * hs, g0 = g(s0), g1 = g(s0 + hs);
+  tab[k] = make_float2((float)g0, (float)((g1 - g0) / hs));
+}
+
+// Short range (Coulomb with the overlap clamp minus the erf field) over nearest-image neighbours
+// closer than r_max, added to the long-range part; result in units of the x quantum.  One
+// workgroup per cell: the records of the 27 neighbouring cells are staged in LDS (in chunks when
+// they exceed it); the cell's targets take one lane each in every wave, and the waves split the
+// staged sources, combined in LDS in a fixed order.  FP32: branch-free tabulated profile
+// (overlapping pairs, which are rare, take the exact clamp); FP64: the exact expressions.
+template <class Real>
+__global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phys ph, P3mDev m,
+                                                             const int32_t *__restrict__ starts,
+                                                             const int32_t *__restrict__ sorted,
+                                                             const SrRec<Real> *__restrict__ rec,
+                                                             const double *__restrict__ slong,
+                                                             const float2 *__restrict__ tab) {
   using Pos = typename Prec<Real>::Pos;
   using SPos = typename std::make_signed<Pos>::type;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ph.N) return;
-  const int3 c = sr_cell<Real>(st, ph, m, i);
-  const Pos xi = st.px[i], yi = st.py[i], zi = st.pz[i];
-  const double di = st.d[i];
-  const double a = m.alpha, c2 = 2.0 * m.alpha / sqrt(M_PI), rmax2 = m.rmax * m.rmax;
-  double sx = 0.0, sy = 0.0, sz = 0.0;
-  for (int ox = -1; ox <= 1; ++ox) {   // ncx >= 3: the three x neighbours are distinct cells
-    int cx = c.x + ox;
-    cx = cx < 0 ? cx + m.ncx : (cx >= m.ncx ? cx - m.ncx : cx);
-    for (int cy = max(c.y - 1, 0); cy <= min(c.y + 1, m.ncy - 1); ++cy)
-      for (int cz = max(c.z - 1, 0); cz <= min(c.z + 1, m.ncy - 1); ++cz) {
-        const int id = (cx * m.ncy + cy) * m.ncy + cz;
-        for (int k = starts[id]; k < starts[id + 1]; ++k) {
-          const int j = sorted[k];
-          if (j == i) continue;
-          const double q = (double)st.js[j].q;
-          if (q == 0.0) continue;
-          const double dx = (double)(SPos)(xi - st.px[j]) * ph.ux;
-          const double dy = (double)((SPos)yi - (SPos)st.py[j]) * ph.ur;
-          const double dz = (double)((SPos)zi - (SPos)st.pz[j]) * ph.ur;
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 >= rmax2 || r2 <= 0.0) continue;
-          const double r = sqrt(r2);
-          const double dij = 0.5 * (di + st.d[j]);
-          const double rc = fmax(r, dij);
-          const double full = 1.0 / (rc * rc);
-          const double lng = erf(a * r) / r2 - c2 * exp(-a * a * r2) / r;
-          const double f = q * (full - lng) / r;
-          sx += f * dx;
-          sy += f * dy;
-          sz += f * dz;
-        }
-      }
+  constexpr int CAP = kSrLds / sizeof(SrRec<Real>);
+  __shared__ SrRec<Real> src[CAP];
+  __shared__ Real part[kSrWaves][3][64];
+  __shared__ int32_t rb[27], rn[27], roff[28];
+  const int c = blockIdx.x;
+  const int cz = c % m.ncy, cy = (c / m.ncy) % m.ncy, cx = c / (m.ncy * m.ncy);
+  const int t0 = starts[c], nt = starts[c + 1] - t0;
+  if (nt == 0) return;   // uniform: the whole workgroup leaves
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x < 27) {
+    const int ox = (int)threadIdx.x / 9 - 1, oy = ((int)threadIdx.x / 3) % 3 - 1, oz = (int)threadIdx.x % 3 - 1;
+    int x = cx + ox;
+    x = x < 0 ? x + m.ncx : (x >= m.ncx ? x - m.ncx : x);
+    const int y = cy + oy, z = cz + oz;
+    int b = 0, n = 0;
+    if (y >= 0 && y < m.ncy && z >= 0 && z < m.ncy) {
+      const int id = (x * m.ncy + y) * m.ncy + z;
+      b = starts[id];
+      n = starts[id + 1] - b;
+    }
+    rb[threadIdx.x] = b;
+    rn[threadIdx.x] = n;
   }
-  // metres^-2 -> units of the x quantum (the direct kernels' convention)
-  const double u2 = ph.ux * ph.ux;
-  st.cx[i] = Real((slong[i] + sx) * u2);
-  st.cy[i] = Real((slong[ph.N + i] + sy) * u2);
-  st.cz[i] = Real((slong[2 * (int64_t)ph.N + i] + sz) * u2);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    roff[0] = 0;
+    for (int k = 0; k < 27; ++k) roff[k + 1] = roff[k] + rn[k];
+  }
+  __syncthreads();
+  const int total = roff[27];
+  const Real ux = Real(ph.ux), ur = Real(ph.ur);
+  const Real a = Real(m.alpha), c2 = Real(2.0 * m.alpha / sqrt(M_PI)), rmax2 = Real(m.rmax * m.rmax);
+  const float tscale = (float)(kSrTable / (m.alpha * m.rmax));
+  for (int tb = 0; tb < nt; tb += 64) {
+    const int kt = tb + lane;
+    const bool has = kt < nt;
+    const SrRec<Real> me = rec[t0 + (has ? kt : 0)];
+    Real sx = 0, sy = 0, sz = 0;
+    for (int cb = 0; cb < total; cb += CAP) {
+      const int n = min(CAP, total - cb);
+      __syncthreads();
+      for (int e = threadIdx.x; e < n; e += 64 * kSrWaves) {
+        const int g = cb + e;
+        int k = 0;
+        while (roff[k + 1] <= g) ++k;
+        src[e] = rec[rb[k] + (g - roff[k])];
+      }
+      __syncthreads();
+      for (int e = w; e < n; e += kSrWaves) {
+        const SrRec<Real> s = src[e];
+        const Real dx = Real((SPos)(me.x - s.x)) * ux;
+        const Real dy = Real((SPos)me.y - (SPos)s.y) * ur;
+        const Real dz = Real((SPos)me.z - (SPos)s.z) * ur;
+        const Real r2 = dx * dx + dy * dy + dz * dz;
+        const bool in = r2 < rmax2 && r2 > Real(0);
+        const Real dij = Real(0.5) * (me.d + s.d);
+        Real f;
+        if constexpr (sizeof(Real) == 4) {
+          const float inv = __builtin_amdgcn_rsqf(in ? r2 : 1.0f);
+          const float r = r2 * inv;
+          const float u = fminf(a * r * tscale, (float)(kSrTable - 1));
+          const int k = (int)u;
+          const float2 tv = tab[k];
+          f = in ? s.q * fmaf(u - (float)k, tv.y / tscale, tv.x) * (inv * inv * inv) : 0.0f;
+          if (in && r < dij) {
+            // overlapping pair: clamped Coulomb minus the erf field, exactly
+            const float gg = c2 * expf(-a * a * r2) / r;
+            f = s.q * (1.0f / (dij * dij) - (erff(a * r) / r2 - gg)) / r;
+          }
+        } else {
+          f = 0.0;
+          if (in) {
+            const double r = sqrt(r2);
+            const double gg = c2 * exp(-a * a * r2) / r;
+            f = (r >= dij ? erfc(a * r) / r2 + gg : 1.0 / (dij * dij) - (erf(a * r) / r2 - gg)) * s.q / r;
+          }
+        }
+        sx += f * dx;
+        sy += f * dy;
+        sz += f * dz;
+      }
+    }
+    part[w][0][lane] = sx;
+    part[w][1][lane] = sy;
+    part[w][2][lane] = sz;
+    __syncthreads();
+    if (w == 0 && has) {
+      double ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll
+      for (int q = 0; q < kSrWaves; ++q) {
+        ax += (double)part[q][0][lane];
+        ay += (double)part[q][1][lane];
+        az += (double)part[q][2][lane];
+      }
+      const int i = sorted[t0 + kt];
+      const double u2 = ph.ux * ph.ux;
+      st.cx[i] = Real((slong[i] + ax) * u2);
+      st.cy[i] = Real((slong[ph.N + i] + ay) * u2);
+      st.cz[i] = Real((slong[2 * (int64_t)ph.N + i] + az) * u2);
+    }
+    __syncthreads();
+  }
 }
 
 int ilog2(int n) {
@@ -378,6 +486,7 @@ void p3m_setup_green(const P3mDev &m, double L, int images, hipStream_t s) {
   hipLaunchKernelGGL(k_p3m_green, dim3(g), dim3(256), 0, s, m, L, images, m.ghat[0], m.ghat[1], m.ghat[2]);
   for (int c = 0; c < 3; ++c) fft3d(m, m.ghat[c], -1, s);
   hipLaunchKernelGGL(k_p3m_deconv, dim3(g), dim3(256), 0, s, m, m.ghat[0], m.ghat[1], m.ghat[2]);
+  hipLaunchKernelGGL(k_p3m_table, dim3((kSrTable + 255) / 256), dim3(256), 0, s, m, m.table);
 }
 
 template <class Real> void launch_p3m(const State<Real> &st, const Phys &ph, const P3mDev &m, hipStream_t s) {
@@ -399,7 +508,10 @@ template <class Real> void launch_p3m(const State<Real> &st, const Phys &ph, con
   hipLaunchKernelGGL(k_p3m_scatter, dim3(gp), dim3(256), 0, s, ph.N, m.cell_of, m.fill, m.sorted);
   hipLaunchKernelGGL(k_p3m_sort, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, ncell, m.starts, m.sorted,
                      m.counts);
-  hipLaunchKernelGGL((k_p3m_short<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.starts, m.sorted, m.slong);
+  SrRec<Real> *rec = (SrRec<Real> *)m.rec;
+  hipLaunchKernelGGL((k_p3m_records<Real>), dim3(gp), dim3(256), 0, s, st, ph, m.sorted, rec);
+  hipLaunchKernelGGL((k_p3m_short<Real>), dim3(ncell), dim3(64 * kSrWaves), 0, s, st, ph, m, m.starts, m.sorted, rec,
+                     m.slong, m.table);
 }
 
 template void launch_p3m<float>(const State<float> &, const Phys &, const P3mDev &, hipStream_t);
