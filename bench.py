@@ -275,7 +275,7 @@ P3M_CONFIGS = {"single-65k": dict(mesh_x=128, mesh_yz=64, alpha_h=0.5, rmax_alph
                "large-1m": dict(mesh_x=256, mesh_yz=128, alpha_h=0.5, rmax_alpha=3.5)}
 
 
-def p3m_run(steps: int = 5) -> dict:
+def p3m_run(steps: int = 5, names=None) -> dict:
     """P3M electrostatics (the x-periodic lattice sum, O(N log N)) against the direct symmetric sums
     (nearest image, O(N^2)): per-step Coulomb-phase time of the full step on the single-65k and
     large-1m workloads."""
@@ -284,6 +284,8 @@ def p3m_run(steps: int = 5) -> dict:
     from synthetic import make_workload
     out = {}
     for name, cfg in P3M_CONFIGS.items():
+        if names is not None and name not in names:
+            continue
         w = make_workload(name)
         field = w.field()
         res = {"particles": w.n_particles, "mesh": [cfg["mesh_x"], 2 * cfg["mesh_yz"], 2 * cfg["mesh_yz"]],
@@ -328,7 +330,11 @@ def main():
                     help="steps timed for the batched Monte Carlo workload (0 disables it)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run one device-to-device copy of this size (reference for HBM counters)")
+    ap.add_argument("--p3m-workloads", default=",".join(P3M_CONFIGS),
+                    help="workloads of the p3m leg (comma-separated)")
+    ap.add_argument("--p3m-steps", type=int, default=5, help="steps timed per workload in the p3m leg")
     args = ap.parse_args()
+    p3m_names = args.p3m_workloads.split(",")
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding is described "
                                    "in DESIGN.md and not implemented", "n_gpus": args.gpus}))
@@ -349,7 +355,7 @@ def main():
         if "lf" in legs:
             out["lf"] = lf_run()
         if "p3m" in legs:
-            out["p3m"] = p3m_run()
+            out["p3m"] = p3m_run(args.p3m_steps, p3m_names)
         print(json.dumps(out), flush=True)
         return
 
@@ -448,7 +454,7 @@ def main():
         if "lf" in legs:
             out["lf"] = lf_run()
         if "p3m" in legs:
-            out["p3m"] = p3m_run()
+            out["p3m"] = p3m_run(args.p3m_steps, p3m_names)
     if cb is not None:
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline"]["value"] = round(cb["value"], 2)

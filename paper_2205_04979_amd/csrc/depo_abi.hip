@@ -594,7 +594,9 @@ depo_status do_seed(depo_ctx *ctx, const depo_sample_params *sp, const double *h
     }
     HIP_TRY(hipGetLastError());
   }
-  // initial force evaluation at x^0 (and v^0 = u_f(x^0) when no velocity is given)
+  // v^0 = u_f(x^0) when no velocity is given, before the initial force evaluation at x^0
+  // (collision damping reads v^0 of the neighbours)
+  if (!hv) launch_finish<Real>(st, ctx->ph, F_FLUID_ONLY, s);
   launch_prepare<Real>(st, ctx->ph, prepare_mode(ctx) | P_SEED, s);
   enqueue_forces<Real>(ctx, s);
   launch_finish<Real>(st, ctx->ph, hv ? 0 : F_V_FROM_FLUID, s);

@@ -148,7 +148,9 @@ __global__ __launch_bounds__(256) void k_prepare(State<Real> st, Phys ph, int mo
 // (+ body) at the new positions, gather u_f(x^{n+1}), half kick, smoothed tally.
 // Without F_KICK it only evaluates the acceleration and the fluid velocity
 // (seed / diagnostic force evaluation); with F_V_FROM_FLUID the velocity is set
-// to the local fluid velocity.
+// to the local fluid velocity.  F_FLUID_ONLY sets u and v = u_f(x) and nothing
+// else: the seed runs it before the first force evaluation, whose collision
+// damping reads the velocities of neighbours.
 template <class Real>
 __global__ __launch_bounds__(256) void k_finish(State<Real> st, Phys ph, int mode) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -156,6 +158,13 @@ __global__ __launch_bounds__(256) void k_finish(State<Real> st, Phys ph, int mod
   if ((mode & F_KICK) && i == 0) *st.nstep += 1;
   if (i >= ph.N) return;
   if (st.dep[i] != 0) return;
+  if (mode & F_FLUID_ONLY) {
+    Real u[3];
+    gather<Real>(st.field, ph.nx, ph.ny, ph.nz, st.px[i], st.py[i], st.pz[i], u);
+    st.ux[i] = u[0]; st.uy[i] = u[1]; st.uz[i] = u[2];
+    st.vx[i] = u[0]; st.vy[i] = u[1]; st.vz[i] = u[2];
+    return;
+  }
   const int s = st.sid[i];
   const SampleDev sp = st.samples[s];
   const double d = st.d[i];

@@ -8,7 +8,7 @@ namespace depo {
 // k_prepare modes
 enum : int { P_KICK_DRIFT = 1, P_COULOMB = 2, P_CELLS = 4, P_SEED = 8 };
 // k_finish modes
-enum : int { F_KICK = 1, F_V_FROM_FLUID = 2 };
+enum : int { F_KICK = 1, F_V_FROM_FLUID = 2, F_FLUID_ONLY = 4 };
 
 template <class Real> void launch_prepare(const State<Real> &st, const Phys &ph, int mode, hipStream_t s);
 template <class Real> void launch_finish(const State<Real> &st, const Phys &ph, int mode, hipStream_t s);

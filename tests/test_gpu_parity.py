@@ -85,6 +85,55 @@ def test_fp64_dense_cluster_contacts_and_neighbours():
     assert np.max(np.linalg.norm(g["a"][al] - ora.a[al], axis=1) / (np.linalg.norm(ora.a[al], axis=1) + 1e-3)) < 1e-7
 
 
+@pytest.mark.parametrize("real_bytes", [8, 4])
+def test_seed_without_velocity_ignores_stale_workspace(real_bytes):
+    """Seeding with v^0 = u_f(x^0) into a workspace that holds NaN bytes from earlier use: the first
+    force evaluation (collision damping reads the neighbours' v^0) equals the oracle's."""
+    import torch
+    from oracle.sim import OracleSim
+    from tests.gpu_common import make_sim
+    rng = np.random.default_rng(23)
+    n = 300
+    p = physical_params(180.0)
+    R, L = p["R"], p["L"]
+    d = rng.choice([5e-6, 10e-6, 20e-6], n)
+    x = np.stack([np.mod(rng.normal(0.0, 50e-6, n), L), R - 0.4e-3 + rng.normal(0, 50e-6, n),
+                  rng.normal(0, 50e-6, n)], 1)
+    q = rng.normal(0, 2e-15, n)
+    sp = np.array([[1.0, 2e-19, 300.0]])
+    f = make_workload("plain-1k", n=4, field_n=16).field()
+    off = np.array([0, n])
+    say("case: stale-workspace seed n=300, real_bytes", real_bytes)
+    probe = make_sim(p, off, f, real_bytes)
+    nbytes = probe._ws.numel()
+    del probe
+    torch.cuda.synchronize()
+    # a block of the workspace's own size, filled with NaN bytes and returned to the caching allocator
+    dirty = torch.full((nbytes,), 0xFF, dtype=torch.uint8, device="cuda")
+    lo, hi = dirty.data_ptr(), dirty.data_ptr() + dirty.numel()
+    torch.cuda.synchronize()
+    del dirty
+    sim = make_sim(p, off, f, real_bytes)
+    if not (lo <= sim._ws.data_ptr() < hi):
+        pytest.skip("the caching allocator did not hand back the dirtied block")
+    sim.init_field(f)
+    sim.seed(sp, x, d, q)
+    ora = OracleSim(p, f, x, d, q, off, sp)
+    g = sim.read()
+    r = x[:, None, :] - x[None, :, :]
+    r[..., 0] -= L * np.round(r[..., 0] / L)
+    gap = np.linalg.norm(r, axis=-1) - 0.5 * (d[:, None] + d[None, :])
+    assert (gap[np.triu_indices(n, 1)] < 0).sum() > 10       # overlapping pairs: damping is active
+    assert np.all(np.isfinite(g["a"])) and np.all(np.isfinite(g["v"]))
+    scale = np.linalg.norm(ora.a, axis=1)
+    if real_bytes == 8:
+        assert np.max(np.linalg.norm(g["a"] - ora.a, axis=1) / (scale + 1e-30)) < 1e-9
+        assert np.max(np.abs(g["v"] - ora.v)) <= 1e-12
+    else:
+        assert np.max(np.linalg.norm(g["a"] - ora.a, axis=1) / (scale + 1e-3 * scale.max())) < 1e-4
+        assert np.max(np.abs(g["v"] - ora.v)) <= 1e-5 * np.abs(ora.v).max()
+
+
 def test_fp64_batched_samples_with_rebound():
     w = make_workload("batched-256", n_samples=5, n_lo=60, n_hi=300, field_n=32)
     f = w.field()
