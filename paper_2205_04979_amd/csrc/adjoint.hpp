@@ -3,6 +3,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "launch.hpp"
 
 namespace depo {
 
@@ -48,6 +49,10 @@ void launch_adj_post(const State<Real> &st, const Phys &ph, const TapeEntry<Real
                      const AdjState<Real> &ad, int mode, hipStream_t s);
 template <class Real>
 void launch_coulomb_vjp(const State<Real> &st, const Phys &ph, const AdjState<Real> &ad, int n_tiles, hipStream_t s);
+// FP32 symmetric form over the forward's item list (ipl, waves of cfg); uses the
+// state's pair accumulators as FP64 scratch and leaves them zero.
+void launch_coulomb_vjp_sym(const State<float> &st, const Phys &ph, const AdjState<float> &ad, int n_diag, int n_off,
+                            const CoulombConfig &cfg, hipStream_t s);
 template <class Real>
 void launch_short_range_vjp(const State<Real> &st, const Phys &ph, const AdjState<Real> &ad, int n_cells, int mode,
                             hipStream_t s);

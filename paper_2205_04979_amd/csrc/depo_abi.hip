@@ -878,7 +878,16 @@ depo_status do_adjoint(depo_ctx *ctx, int n, int ce, const double *hw, double *h
       launch_tape_load<Real>(st, s1, N, false, s);
       rebuild_cells();
       launch_adj_post<Real>(st, ph, s0, s1, pl.ad, 0, s);
-      if (coul) launch_coulomb_vjp<Real>(st, ph, pl.ad, ctx->n_tiles, s);
+      if (coul) {
+        if constexpr (std::is_same<Real, float>::value) {
+          if (ctx->ccfg.symmetric)
+            launch_coulomb_vjp_sym(ctx->sf, ph, pl.ad, ctx->n_diag, ctx->n_off, ctx->ccfg, s);
+          else
+            launch_coulomb_vjp<Real>(st, ph, pl.ad, ctx->n_tiles, s);
+        } else {
+          launch_coulomb_vjp<Real>(st, ph, pl.ad, ctx->n_tiles, s);
+        }
+      }
       if (sr) launch_short_range_vjp<Real>(st, ph, pl.ad, ctx->n_cells, 0, s);
       launch_adj_pre<Real>(st, ph, s0, pl.ad, coul, sr, s);
     }

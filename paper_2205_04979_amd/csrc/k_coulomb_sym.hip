@@ -90,11 +90,13 @@ __device__ __forceinline__ void ring_item(const SymItem &it, const JSrc<float> *
 #pragma unroll
     for (int k = 0; k < IPL; ++k) sx[k] = sy[k] = sz[k] = 0.0f;
     uint64_t nearmask = 0;
-#pragma unroll 4
-    for (int t = 0; t < 64; ++t) {
+    // one ring step; target kskip (if any) is skipped: in a diagonal item, step 0 of the round
+    // that holds target chunk k pairs every lane with itself (zero force, but never "near")
+    auto step = [&](int t, int kskip) {
       const JSrc<float> s = rs[t];
 #pragma unroll
       for (int k = 0; k < IPL; ++k) {
+        if (k == kskip) continue;
         const float dx = sdiff(xi[k], s.x);
         const float dy = yi[k] - s.y;
         const float dz = zi[k] - s.z;
@@ -118,6 +120,15 @@ __device__ __forceinline__ void ring_item(const SymItem &it, const JSrc<float> *
         ry = dpp<kWaveRol1>(ry);
         rz = dpp<kWaveRol1>(rz);
       }
+    };
+    if constexpr (REACT) {
+#pragma unroll 4
+      for (int t = 0; t < 64; ++t) step(t, -1);
+    } else {
+      const int kself = (jb - w * 64 * IPL) >> 6;   // wave-uniform; outside [0, IPL) when no self pair
+      step(0, kself);
+#pragma unroll 3
+      for (int t = 1; t < 64; ++t) step(t, -1);
     }
     if (nearmask) {
       // exact overlap clamp for this round, both sides: r / (|r| max(|r|, d_ij)^2), zero at r = 0

@@ -257,8 +257,10 @@ class Simulation(Context):
 
     def set_kernel_config(self, targets_per_lane: int, waves: int, block: int, mode=None, use_graph: bool = True,
                           compensated: Optional[bool] = None):
-        """Pair-kernel shape and mode: PAIR_PLAIN, PAIR_KAHAN or PAIR_SYMMETRIC (FP32); the default is Kahan in
-        FP32 and plain in FP64.  ``compensated`` (bool) is accepted in place of ``mode`` for the one-sided modes."""
+        """Pair-kernel shape and mode: PAIR_PLAIN, PAIR_KAHAN or PAIR_SYMMETRIC (FP32).  ``mode=None`` selects
+        the one-sided Kahan mode in FP32 and plain in FP64 (before any call the library runs the symmetric
+        mode, shape (4, 2, 64), in FP32).  ``compensated`` (bool) is accepted in place of ``mode`` for the
+        one-sided modes.  The FP32 adjoint uses the symmetric pair adjoint when the mode is symmetric."""
         if mode is None:
             mode = (PAIR_KAHAN if compensated else PAIR_PLAIN) if compensated is not None else (
                 PAIR_KAHAN if self.real_bytes == 4 else PAIR_PLAIN)

@@ -145,6 +145,32 @@ def test_fp32_adjoint_close_to_fp64_adjoint():
     assert np.allclose(g[4][:, :2], g[8][:, :2], rtol=2e-3, atol=0)
 
 
+@pytest.mark.parametrize("shape", [(4, 1), (2, 2), (4, 2), (8, 1)])
+def test_fp32_symmetric_pair_adjoint_matches_one_sided(shape):
+    """Two samples of uneven size (several tiles each, ragged last tile): the symmetric pair adjoint
+    (each pair once, antisymmetric reaction) agrees with the one-sided pair adjoint and with the FP64
+    adjoint; two symmetric runs agree to FP64 rounding of the atomic combination."""
+    from paper_2205_04979_amd.depo import PAIR_KAHAN, PAIR_SYMMETRIC
+    p, f, x, d, q, off, sp, v0 = sensitive_case(n_per=1000, seed=12)
+    off = np.array([0, 1300, 2000])
+    n, ce = 20, 10
+    say("case: symmetric pair adjoint, shape", shape, "samples", np.diff(off).tolist())
+    g = {}
+    for key in ("sym", "sym2", "one", "fp64"):
+        sim = gpu_sim(p, f, off, 8 if key == "fp64" else 4)
+        if key.startswith("sym"):
+            sim.set_kernel_config(shape[0], shape[1], 64, mode=PAIR_SYMMETRIC)
+        elif key == "one":
+            sim.set_kernel_config(1, 8, 32, mode=PAIR_KAHAN)
+        sim.seed(sp, x, d, q, v=v0)
+        g[key] = sim.adjoint(n, ce)[:, :2]
+    say({k: v.tolist() for k, v in g.items()})
+    assert np.all(np.abs(g["fp64"]) > 0)
+    assert np.allclose(g["sym"], g["sym2"], rtol=1e-12, atol=0)
+    assert np.allclose(g["sym"], g["one"], rtol=5e-4, atol=0)
+    assert np.allclose(g["sym"], g["fp64"], rtol=2e-3, atol=0)
+
+
 def test_autograd_function_backward():
     import torch
     from paper_2205_04979_amd.depo import DepositionFn
