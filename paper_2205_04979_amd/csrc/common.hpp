@@ -39,6 +39,9 @@ struct SampleDev {
   int32_t ncx, ncy, ncz;          // cell grid
   int32_t cell_base;              // first global cell id of this sample
   double charge_scale, hamaker, temperature;
+  // short-range reach (largest centre distance with a contact or cohesive force, plus a
+  // relative margin of 1e-5 for rounding) in cell widths along x and along y/z
+  double sr_tx, sr_tr;
 };
 
 // One work item of the pair kernel: targets [i0, i0+icount) of a sample whose
@@ -162,6 +165,46 @@ __device__ __forceinline__ int box_cell(int64_t y, int n) {
   uint64_t lo = u * (uint64_t)n;
   uint64_t c = (hi << 1) | (lo >> 63);
   return c >= (uint64_t)n ? n - 1 : (int)c;
+}
+
+// box_cell with the position's fraction of its cell width (0 for a clamped position).
+__device__ __forceinline__ int box_cell_frac(int32_t y, int n, double &f) {
+  int64_t u = (int64_t)y + (1ll << 30);
+  if (u <= 0) { f = 0.0; return 0; }
+  int64_t t = u * (int64_t)n;
+  int64_t c = t >> 31;
+  if (c >= n) { f = 0.0; return n - 1; }
+  f = (double)(t & ((1ll << 31) - 1)) * 0x1p-31;
+  return (int)c;
+}
+__device__ __forceinline__ int box_cell_frac(int64_t y, int n, double &f) {
+  if (y <= -(1ll << 62)) { f = 0.0; return 0; }
+  uint64_t u = (uint64_t)(y + (1ll << 62));
+  uint64_t hi = __umul64hi(u, (uint64_t)n);
+  uint64_t lo = u * (uint64_t)n;
+  uint64_t c = (hi << 1) | (lo >> 63);
+  if (c >= (uint64_t)n) { f = 0.0; return n - 1; }
+  f = (double)(lo & ((1ull << 63) - 1)) * 0x1p-63;
+  return (int)c;
+}
+
+// A partner within the reach lies in the neighbour cell below (above) along an axis only
+// if the particle is closer than the reach to that face: bit 0 lower, bit 1 upper.
+__device__ __forceinline__ int reach_sides(double f, double thr) {
+  return (f < thr ? 1 : 0) | (1.0 - f < thr ? 2 : 0);
+}
+
+// Cell of a particle and the neighbour cells its short-range walk must visit.
+template <class Pos>
+__device__ __forceinline__ void short_range_cells(Pos px, Pos py, Pos pz, const SampleDev &sp, int &cx, int &cy,
+                                                  int &cz, int &mx, int &my, int &mz) {
+  double fx, fy, fz;
+  cx = frac_cell(px, sp.ncx, fx);
+  cy = box_cell_frac(as_signed(py), sp.ncy, fy);
+  cz = box_cell_frac(as_signed(pz), sp.ncz, fz);
+  mx = reach_sides(fx, sp.sr_tx);
+  my = reach_sides(fy, sp.sr_tr);
+  mz = reach_sides(fz, sp.sr_tr);
 }
 
 __device__ __forceinline__ int x_cell(uint32_t x, int n) { return (int)(((uint64_t)x * (uint64_t)n) >> 32); }

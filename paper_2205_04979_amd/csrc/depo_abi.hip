@@ -486,6 +486,8 @@ depo_status build_samples(depo_ctx *ctx, const depo_sample_params *sp, const dou
     sd.ncx = ncx;
     sd.ncy = ncy;
     sd.ncz = ncy;
+    sd.sr_tx = reach * (1.0 + 1e-5) * ncx / p.L;
+    sd.sr_tr = reach * (1.0 + 1e-5) * ncy / (2.0 * p.R);
     sd.cell_base = (int32_t)cells;
     cells += (int64_t)ncx * ncy * ncy;
   }
@@ -817,7 +819,8 @@ size_t carve_adjoint(const depo_ctx *ctx, char *base, int n_ckpt, int seg_len, A
   pl.ckpt.clear();
   pl.tape.clear();
   for (int k = 0; k < n_ckpt; ++k) pl.ckpt.push_back(entry(false));
-  for (int k = 0; k < seg_len; ++k) pl.tape.push_back(entry(false));   // tape[k] holds S_{k+1} of a segment
+  // tape[k] holds S_{k+1} of a segment; its last state is the next checkpoint (or the final state)
+  for (int k = 0; k < seg_len - 1; ++k) pl.tape.push_back(entry(false));
   pl.fin = entry(true);
   AdjState<Real> &a = pl.ad;
   a.lam_ell = (Real *)take(N * sizeof(Real));
@@ -867,14 +870,19 @@ depo_status do_adjoint(depo_ctx *ctx, int n, int ce, const double *hw, double *h
   };
   for (int seg = K - 1; seg >= 0; --seg) {
     const int len = std::min(ce, n - seg * ce);
-    launch_tape_load<Real>(st, pl.ckpt[seg], N, false, s);
-    for (int k = 0; k < len; ++k) {
-      enqueue_step<Real>(ctx, s);
-      launch_tape_store<Real>(st, pl.tape[k], N, false, s);
+    // the segment's last state is the next checkpoint (or the final state): the forward is
+    // bitwise deterministic, so only the len - 1 states before it are recomputed
+    const TapeEntry<Real> &last = seg + 1 < K ? pl.ckpt[seg + 1] : pl.fin;
+    if (len > 1) {
+      launch_tape_load<Real>(st, pl.ckpt[seg], N, false, s);
+      for (int k = 0; k < len - 1; ++k) {
+        enqueue_step<Real>(ctx, s);
+        launch_tape_store<Real>(st, pl.tape[k], N, false, s);
+      }
     }
     for (int k = len - 1; k >= 0; --k) {
       const TapeEntry<Real> &s0 = k == 0 ? pl.ckpt[seg] : pl.tape[k - 1];
-      const TapeEntry<Real> &s1 = pl.tape[k];
+      const TapeEntry<Real> &s1 = k == len - 1 ? last : pl.tape[k];
       launch_tape_load<Real>(st, s1, N, false, s);
       rebuild_cells();
       launch_adj_post<Real>(st, ph, s0, s1, pl.ad, 0, s);

@@ -383,7 +383,8 @@ __global__ __launch_bounds__(256) void k_short_range_vjp(State<Real> st, Phys ph
   const int i = st.cell_idx[t];
   const SampleDev sp = st.samples[st.sid[i]];
   const auto px = st.px[i], py = st.py[i], pz = st.pz[i];
-  const int cx = x_cell(px, sp.ncx), cy = box_cell(as_signed(py), sp.ncy), cz = box_cell(as_signed(pz), sp.ncz);
+  int cx, cy, cz, mx, my, mz;
+  short_range_cells(px, py, pz, sp, cx, cy, cz, mx, my, mz);
   const Real di = Real(st.d[i]);
   const Real mi = Real(ph.mass_coef) * di * di * di;
   const Real A = Real(sp.hamaker);
@@ -394,13 +395,17 @@ __global__ __launch_bounds__(256) void k_short_range_vjp(State<Real> st, Phys ph
   const Real vi[3] = {ad.vp[0][i], ad.vp[1][i], ad.vp[2][i]};
   Real xb[3] = {0, 0, 0}, vb[3] = {0, 0, 0};
   double gA = 0.0;
+  // only the neighbour cells whose shared face is closer than the reach can hold a partner
   for (int ox = -1; ox <= 1; ++ox) {
+    if ((ox < 0 && !(mx & 1)) || (ox > 0 && !(mx & 2))) continue;
     int xx = cx + ox;
     xx = xx < 0 ? xx + sp.ncx : (xx >= sp.ncx ? xx - sp.ncx : xx);
     for (int oy = -1; oy <= 1; ++oy) {
+      if ((oy < 0 && !(my & 1)) || (oy > 0 && !(my & 2))) continue;
       const int yy = cy + oy;
       if (yy < 0 || yy >= sp.ncy) continue;
       for (int oz = -1; oz <= 1; ++oz) {
+        if ((oz < 0 && !(mz & 1)) || (oz > 0 && !(mz & 2))) continue;
         const int zz = cz + oz;
         if (zz < 0 || zz >= sp.ncz) continue;
         const int c = sp.cell_base + (xx * sp.ncy + yy) * sp.ncz + zz;
