@@ -69,7 +69,10 @@ def cpu_baseline(w, field, n_targets: int):
     _SIM = OracleSim(w.params, field, w.x, w.d, w.qbase, w.offsets, w.sample_params, evaluate=False)
     cores = min(16, len(os.sched_getaffinity(0)))
     rng = np.random.default_rng(12345)
+    n_targets = min(n_targets, w.n_particles)
     targets = np.sort(rng.choice(w.n_particles, n_targets, replace=False))
+    which = (f"all {n_targets} particles" if n_targets == w.n_particles
+             else f"{n_targets} randomly chosen particles")
     chunks = np.array_split(targets, cores * 2)
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
@@ -77,7 +80,7 @@ def cpu_baseline(w, field, n_targets: int):
         pool.map(_run_chunk, chunks)
     wall = time.perf_counter() - t0
     return dict(value=n_targets / wall, unit="particle-steps/s", cores=cores, kind="oracle",
-                sample=f"{n_targets} randomly chosen particles of the {w.name} workload, one full step each "
+                sample=f"{which} of the {w.name} workload, one full step each "
                        f"(drag kicks, gather, all {w.n_particles} Coulomb sources, short-range and wall terms), "
                        f"FP64 NumPy, {cores} processes",
                 seconds=wall)
@@ -321,7 +324,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="single-65k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-targets", type=int, default=4096)
+    ap.add_argument("--cpu-targets", type=int, default=65536,
+                    help="particles of the workload the CPU oracle steps once (capped at the workload size)")
     ap.add_argument("--kernel", default=None, help="pair-kernel shape ipl,waves,block (skips autotuning)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--legs", default="single,batched,adjoint,rebound,lf,p3m",

@@ -134,6 +134,73 @@ def test_seed_without_velocity_ignores_stale_workspace(real_bytes):
         assert np.max(np.abs(g["v"] - ora.v)) <= 1e-5 * np.abs(ora.v).max()
 
 
+def _cell_grid(R, L, n, reach):
+    """The short-range cell grid the library builds for one sample (cells sized for about one particle)."""
+    h = max(reach, (4.0 * R * R * L / max(n, 1)) ** (1.0 / 3.0))
+    while True:
+        ncx = max(3, int(np.floor(L / h)))
+        ncy = max(1, int(np.floor(2.0 * R / h)))
+        if ncx * ncy * ncy <= n + 64:
+            return ncx, ncy
+        h *= 1.05
+
+
+@pytest.mark.parametrize("real_bytes", [8, 4])
+def test_short_range_pairs_across_cell_faces(real_bytes):
+    """Pairs straddling x, y and z cell faces (and the periodic seam), closer to the face than the reach:
+    the walk visits a neighbour cell only when the face is within the reach, and still finds every pair
+    (counts equal brute force; pairs well outside the range are not counted); accelerations match the oracle."""
+    rng = np.random.default_rng(31)
+    p = physical_params(180.0)
+    R, L = p["R"], p["L"]
+    n_pairs, n_free = 150, 100
+    n = 2 * n_pairs + n_free
+    d = np.full(n, 10e-6)
+    reach = 1.25 * d.max()
+    ncx, ncy = _cell_grid(R, L, n, reach)
+    hx, hy = L / ncx, 2 * R / ncy
+    x = np.zeros((n, 3))
+    gaps = np.where(np.arange(n_pairs) % 3 == 2, rng.uniform(0.3, 0.6, n_pairs), rng.uniform(-0.05, 0.2, n_pairs)) * d[0]
+    for k in range(n_pairs):
+        axis = k % 3
+        c = np.array([rng.uniform(0, L), rng.uniform(-0.5 * R, 0.5 * R), rng.uniform(-0.5 * R, 0.5 * R)])
+        if axis == 0:
+            c[0] = rng.integers(0, ncx) * hx                       # includes the seam x = 0
+        else:
+            j = rng.integers(ncy // 4, 3 * ncy // 4 + 1)
+            c[axis] = -R + j * hy
+        # a face point c; the pair centre straddles it, direction mostly across the face
+        u = rng.normal(0, 0.3, 3)
+        u[axis] = 1.0 if rng.random() < 0.5 else -1.0
+        u /= np.linalg.norm(u)
+        sep = d[0] + gaps[k]
+        off = rng.uniform(0.1, 0.9) * sep
+        x[2 * k] = c + u * off
+        x[2 * k + 1] = c - u * (sep - off)
+    x[2 * n_pairs:] = np.stack([rng.uniform(0, L, n_free), rng.uniform(-0.6 * R, 0.6 * R, n_free),
+                                rng.uniform(-0.6 * R, 0.6 * R, n_free)], 1)
+    x[:, 0] = np.mod(x[:, 0], L)
+    q = rng.normal(0, 2e-15, n)
+    sp = np.array([[1.0, 2e-19, 300.0]])
+    f = make_workload("plain-1k", n=4, field_n=16).field()
+    off_ = np.array([0, n])
+    say("case: pairs across cell faces, grid", ncx, ncy, "real_bytes", real_bytes)
+    sim, ora = seeded_pair(p, f, x, d, q, off_, sp, real_bytes, v0=np.zeros((n, 3)))
+    g = sim.read()
+    r = x[:, None, :] - x[None, :, :]
+    r[..., 0] -= L * np.round(r[..., 0] / L)
+    dist = np.linalg.norm(r, axis=-1)
+    gap = dist - 0.5 * (d[:, None] + d[None, :])
+    near = (gap <= 0.25 * np.minimum(d[:, None], d[None, :])) & (dist > 0)
+    assert near.sum() >= 150                                  # the in-range pairs (both members)
+    assert np.array_equal(g["neighbours"], near.sum(axis=1))
+    scale = np.linalg.norm(ora.a, axis=1)
+    if real_bytes == 8:
+        assert np.max(np.linalg.norm(g["a"] - ora.a, axis=1) / (scale + 1e-30)) < 1e-9
+    else:
+        assert np.max(np.linalg.norm(g["a"] - ora.a, axis=1) / (scale + 1e-3 * scale.max())) < 1e-4
+
+
 def test_fp64_batched_samples_with_rebound():
     w = make_workload("batched-256", n_samples=5, n_lo=60, n_hi=300, field_n=32)
     f = w.field()
