@@ -267,8 +267,9 @@ depo_status depo_state_download(depo_ctx *ctx, void *h_blob, size_t bytes, depo_
 depo_status depo_state_upload(depo_ctx *ctx, const void *h_blob, size_t bytes, depo_stream stream);
 
 /* Device bytes needed by depo_adjoint for n_steps and a checkpoint interval
- * (1 <= ckpt_every <= n_steps): ceil(n_steps / ckpt_every) stored states, one
- * segment of per-step states and the adjoint arrays.  Host only. */
+ * (1 <= ckpt_every <= n_steps): ceil(n_steps / ckpt_every) stored states, the
+ * ckpt_every - 1 per-step states of one segment (its last state is the next
+ * checkpoint), the final state and the adjoint arrays.  Host only. */
 depo_status depo_adjoint_workspace_bytes(const depo_ctx *ctx, int32_t n_steps, int32_t ckpt_every, size_t *bytes);
 
 /* Gradient of J = sum_s w_s J_s, J_s = sum_{i in s} m_i (1 - exp(-l_i)) the
@@ -285,7 +286,10 @@ depo_status depo_adjoint_workspace_bytes(const depo_ctx *ctx, int32_t n_steps, i
  * temperature column is exactly 0 (it enters only the rebound law, which the
  * smoothed tally turns off).  d_adj_work: caller-owned device memory of
  * depo_adjoint_workspace_bytes() bytes, 256-byte aligned.  Synchronises the
- * stream. */
+ * stream.  Pair adjoint: in FP32 with the symmetric pair mode, each unordered
+ * pair is evaluated once and items are combined with FP64 atomic additions, so
+ * repeated calls agree to the rounding of those additions (not bitwise); every
+ * other configuration is bitwise reproducible.  DEPO_E_INVALID in the P3M mode. */
 depo_status depo_adjoint(depo_ctx *ctx, int32_t n_steps, int32_t ckpt_every, const double *h_weights,
                          double *h_grad, void *d_adj_work, size_t bytes, depo_stream stream);
 
