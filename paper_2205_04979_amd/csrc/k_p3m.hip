@@ -103,16 +103,21 @@ __global__ void k_p3m_deconv(P3mDev m, double2 *__restrict__ gx_, double2 *__res
 }
 
 // Complex FFT of length n = 2^log2n along lines of the mesh: line l starts at
-// (l / inner) * outer_stride + (l % inner) * inner_stride, points are point_stride apart.
-// A workgroup transforms kFftLds / n lines through LDS (bit-reversed load, in-place
-// radix-2 butterflies, twiddles exp(sign 2 pi i k / n) from sincospi).
-__global__ __launch_bounds__(256) void k_fft_lines(double2 *__restrict__ data, int n, int log2n, int64_t inner,
+// (l >> log2inner) * outer_stride + (l & (2^log2inner - 1)) * inner_stride, points are
+// point_stride apart.  A workgroup transforms kFftLds / n lines through LDS (bit-reversed load,
+// in-place radix-2 butterflies, twiddles exp(sign 2 pi i k / n) from sincospi).  Every extent is
+// a power of two, so all index arithmetic is shifts and masks.
+constexpr int kFftLog2Lds = 11;
+static_assert((1 << kFftLog2Lds) == kFftLds, "kFftLds is 2^kFftLog2Lds");
+__global__ __launch_bounds__(256) void k_fft_lines(double2 *__restrict__ data, int log2n, int log2inner,
                                                    int64_t inner_stride, int64_t outer_stride, int64_t point_stride,
                                                    int sign, int points_contiguous) {
   __shared__ double2 buf[kFftLds];
   __shared__ double2 tw[kFftLds / 2];
-  const int lpw = kFftLds / n;   // lines per workgroup
-  const int64_t l0 = (int64_t)blockIdx.x * lpw;
+  const int n = 1 << log2n;
+  const int log2lpw = kFftLog2Lds - log2n;   // lines per workgroup: 2^log2lpw
+  const int64_t l0 = (int64_t)blockIdx.x << log2lpw;
+  const int64_t inner_mask = ((int64_t)1 << log2inner) - 1;
   for (int k = threadIdx.x; k < n / 2; k += blockDim.x) {
     double s, c;
     sincospi(2.0 * k / n, &s, &c);
@@ -120,40 +125,45 @@ __global__ __launch_bounds__(256) void k_fft_lines(double2 *__restrict__ data, i
   }
   auto addr = [&](int line, int p) {
     const int64_t l = l0 + line;
-    return (l / inner) * outer_stride + (l % inner) * inner_stride + (int64_t)p * point_stride;
+    return (l >> log2inner) * outer_stride + (l & inner_mask) * inner_stride + (int64_t)p * point_stride;
   };
+  const int lmask = (1 << log2lpw) - 1, pmask = n - 1;
   for (int e = threadIdx.x; e < kFftLds; e += blockDim.x) {
-    const int line = points_contiguous ? e / n : e % lpw;
-    const int p = points_contiguous ? e % n : e / lpw;
+    const int line = points_contiguous ? e >> log2n : e & lmask;
+    const int p = points_contiguous ? e & pmask : e >> log2lpw;
     const int rev = (int)(__brev((unsigned)p) >> (32 - log2n));
-    buf[line * n + rev] = data[addr(line, p)];
+    buf[(line << log2n) + rev] = data[addr(line, p)];
   }
   __syncthreads();
-  for (int len = 2; len <= n; len <<= 1) {
-    const int half = len >> 1, step = n / len;
+  for (int lg = 1; lg <= log2n; ++lg) {
+    const int half = 1 << (lg - 1);
     for (int b = threadIdx.x; b < kFftLds / 2; b += blockDim.x) {
-      const int line = b / (n / 2), k = b % (n / 2);
-      const int pos = k % half;
-      const int i = line * n + (k / half) * len + pos;
+      const int line = b >> (log2n - 1), k = b & ((n >> 1) - 1);
+      const int pos = k & (half - 1);
+      const int i = (line << log2n) + ((k >> (lg - 1)) << lg) + pos;
       const double2 u = buf[i];
-      const double2 v = cmul(tw[pos * step], buf[i + half]);
+      const double2 v = cmul(tw[pos << (log2n - lg)], buf[i + half]);
       buf[i] = make_double2(u.x + v.x, u.y + v.y);
       buf[i + half] = make_double2(u.x - v.x, u.y - v.y);
     }
     __syncthreads();
   }
   for (int e = threadIdx.x; e < kFftLds; e += blockDim.x) {
-    const int line = points_contiguous ? e / n : e % lpw;
-    const int p = points_contiguous ? e % n : e / lpw;
-    data[addr(line, p)] = buf[line * n + p];
+    const int line = points_contiguous ? e >> log2n : e & lmask;
+    const int p = points_contiguous ? e & pmask : e >> log2lpw;
+    data[addr(line, p)] = buf[(line << log2n) + p];
   }
 }
 
 // TSC charge assignment in 64-bit fixed point (units of the per-sample bound 2^-62 sum |q~|).
 template <class Real>
-__global__ void k_p3m_assign(State<Real> st, Phys ph, P3mDev m, unsigned long long *__restrict__ qmesh) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ph.N) return;
+__global__ void k_p3m_assign(State<Real> st, Phys ph, P3mDev m, const int32_t *__restrict__ order,
+                             unsigned long long *__restrict__ qmesh) {
+  // particles taken in short-range cell order, so neighbouring lanes add to nearby nodes (the
+  // integer additions commute: the order does not change the result)
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ph.N) return;
+  const int i = order[k];
   const double q = (double)st.js[i].q;
   if (q == 0.0) return;
   const double qs = *m.q_scale;
@@ -200,10 +210,11 @@ __global__ void k_p3m_mul(P3mDev m, const double2 *__restrict__ a, const double2
 
 // TSC interpolation of one field component (real part of the unnormalised inverse transform).
 template <class Real>
-__global__ void k_p3m_interp(State<Real> st, Phys ph, P3mDev m, const double2 *__restrict__ E,
-                             double *__restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ph.N) return;
+__global__ void k_p3m_interp(State<Real> st, Phys ph, P3mDev m, const int32_t *__restrict__ order,
+                             const double2 *__restrict__ E, double *__restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;   // cell order, for locality of the mesh reads
+  if (k >= ph.N) return;
+  const int i = order[k];
   double gx, gy, gz, wx[3], wy[3], wz[3];
   int ix, iy, iz;
   mesh_coords<Real>(st, ph, m, i, gx, gy, gz);
@@ -282,22 +293,40 @@ __global__ void k_p3m_scatter(int32_t N, const int32_t *__restrict__ cell_of, in
   sorted[atomicAdd(fill + cell_of[i], 1)] = i;
 }
 
-// Particles of each cell in index order (a fixed summation order); the counts are cleared.
-__global__ void k_p3m_sort(int32_t ncell, const int32_t *__restrict__ starts, int32_t *__restrict__ sorted,
-                           int32_t *__restrict__ counts) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncell) return;
-  const int b = starts[c], e = starts[c + 1];
-  for (int k = b + 1; k < e; ++k) {
-    const int v = sorted[k];
-    int j = k - 1;
-    while (j >= b && sorted[j] > v) {
-      sorted[j + 1] = sorted[j];
-      --j;
+// Particles of each cell in index order (a fixed summation order); the counts are cleared.  One
+// workgroup per cell: the cell's indices are staged in LDS and each is written to its rank (the
+// number of smaller indices; indices are distinct).  A cell of more than kSortCap particles is
+// sorted by one thread.
+constexpr int kSortCap = 2048;
+__global__ __launch_bounds__(256) void k_p3m_sort(int32_t ncell, const int32_t *__restrict__ starts,
+                                                  int32_t *__restrict__ sorted, int32_t *__restrict__ counts) {
+  __shared__ int32_t v[kSortCap];
+  const int c = blockIdx.x;
+  const int b = starts[c], n = starts[c + 1] - b;
+  if (threadIdx.x == 0) counts[c] = 0;
+  if (n <= 1) return;   // uniform
+  if (n > kSortCap) {
+    if (threadIdx.x == 0) {
+      for (int k = b + 1; k < b + n; ++k) {
+        const int x = sorted[k];
+        int j = k - 1;
+        while (j >= b && sorted[j] > x) {
+          sorted[j + 1] = sorted[j];
+          --j;
+        }
+        sorted[j + 1] = x;
+      }
     }
-    sorted[j + 1] = v;
+    return;
   }
-  counts[c] = 0;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) v[e] = sorted[b + e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int x = v[e];
+    int rank = 0;
+    for (int k = 0; k < n; ++k) rank += v[k] < x ? 1 : 0;
+    sorted[b + rank] = x;
+  }
 }
 
 // Source record of the short-range pass, in cell-sorted order.
@@ -317,7 +346,9 @@ __global__ void k_p3m_records(State<Real> st, Phys ph, const int32_t *__restrict
   r.y = st.py[i];
   r.z = st.pz[i];
   r.q = st.js[i].q;
-  r.d = Real(st.d[i]);
+  // FP32: the radius in y/z position quanta (the short-range body works in those units);
+  // FP64: the diameter in metres
+  r.d = sizeof(Real) == 4 ? Real(0.5 * st.d[i] * ph.inv_ur) : Real(st.d[i]);
   rec[k] = r;
 }
 
@@ -327,15 +358,18 @@ constexpr int kSrTable = 4096;   // intervals of the tabulated short-range profi
 
 // Short-range force profile g(s) = erfc(s) + (2 s / sqrt(pi)) exp(-s^2), s = alpha r, so that the
 // short-range force of a non-overlapping pair is q g(alpha r) r_vec / r^3; tabulated on
-// [0, alpha r_max] as (value, slope) pairs for linear interpolation (interpolation error below
-// 1e-7 of the pair force: |g''| < 1.2 and the step is alpha r_max / 4096).
+// [0, alpha r_max] in kSrTable intervals as (g at the interval start, increment over the
+// interval) for linear interpolation in the table coordinate u = kSrTable r / r_max
+// (interpolation error below 1e-7 of the pair force: |g''| < 1.2 and the step is
+// alpha r_max / kSrTable); entry kSrTable is (0, 0): pairs at or beyond r_max get nothing.
 __global__ void k_p3m_table(P3mDev m, float2 *__restrict__ tab) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= kSrTable) return;
+  if (k > kSrTable) return;
+  if (k == kSrTable) { tab[k] = make_float2(0.0f, 0.0f); return; }
   const double hs = m.alpha * m.rmax / kSrTable;
   auto g = [](double x) { return erfc(x) + 2.0 / sqrt(M_PI) * x * exp(-x * x); };
   const double s0 = k * hs, g0 = g(s0), g1 = g(s0 + hs);
-  tab[k] = make_float2((float)g0, (float)((g1 - g0) / hs));
+  tab[k] = make_float2((float)g0, (float)(g1 - g0));
 }
 
 // Short range (Coulomb with the overlap clamp minus the erf field) over nearest-image neighbours
@@ -385,7 +419,11 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
   const int total = roff[27];
   const Real ux = Real(ph.ux), ur = Real(ph.ur);
   const Real a = Real(m.alpha), c2 = Real(2.0 * m.alpha / sqrt(M_PI)), rmax2 = Real(m.rmax * m.rmax);
-  const float tscale = (float)(kSrTable / (m.alpha * m.rmax));
+  // FP32 form, in y/z position quanta: x differences scaled by u_x / u_r, alpha per quantum,
+  // table coordinate u = r * tq, the largest contact distance squared
+  const float kx = (float)(ph.ux / ph.ur), aq = (float)(m.alpha * ph.ur), c2q = (float)(2.0 * m.alpha * ph.ur / sqrt(M_PI));
+  const float tq = (float)(kSrTable * ph.ur / m.rmax);
+  const float near2q = (float)(ph.near2 * (ph.ux / ph.ur) * (ph.ux / ph.ur));
   for (int tb = 0; tb < nt; tb += 64) {
     const int kt = tb + lane;
     const bool has = kt < nt;
@@ -394,45 +432,52 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
     for (int cb = 0; cb < total; cb += CAP) {
       const int n = min(CAP, total - cb);
       __syncthreads();
-      for (int e = threadIdx.x; e < n; e += 64 * kSrWaves) {
-        const int g = cb + e;
-        int k = 0;
-        while (roff[k + 1] <= g) ++k;
-        src[e] = rec[rb[k] + (g - roff[k])];
+      // staged entries [cb, cb + n) of the concatenated 27 cell ranges, cell by cell
+      for (int k = 0; k < 27; ++k) {
+        const int lo = max(roff[k], cb), hi = min(roff[k + 1], cb + n);
+        for (int g = lo + (int)threadIdx.x; g < hi; g += 64 * kSrWaves) src[g - cb] = rec[rb[k] + (g - roff[k])];
       }
       __syncthreads();
       for (int e = w; e < n; e += kSrWaves) {
         const SrRec<Real> s = src[e];
-        const Real dx = Real((SPos)(me.x - s.x)) * ux;
-        const Real dy = Real((SPos)me.y - (SPos)s.y) * ur;
-        const Real dz = Real((SPos)me.z - (SPos)s.z) * ur;
-        const Real r2 = dx * dx + dy * dy + dz * dz;
-        const bool in = r2 < rmax2 && r2 > Real(0);
-        const Real dij = Real(0.5) * (me.d + s.d);
-        Real f;
         if constexpr (sizeof(Real) == 4) {
-          const float inv = __builtin_amdgcn_rsqf(in ? r2 : 1.0f);
+          // y/z quanta; r2 floored so that r = 0 (the target itself) gives a finite f times dx = 0
+          const float dx = (float)(int32_t)(me.x - s.x) * kx;
+          const float dy = (float)((int32_t)me.y - (int32_t)s.y);
+          const float dz = (float)((int32_t)me.z - (int32_t)s.z);
+          const float r2 = fmaxf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), 1e-20f);
+          const float inv = __builtin_amdgcn_rsqf(r2);
           const float r = r2 * inv;
-          const float u = fminf(a * r * tscale, (float)(kSrTable - 1));
-          const int k = (int)u;
-          const float2 tv = tab[k];
-          f = in ? s.q * fmaf(u - (float)k, tv.y / tscale, tv.x) * (inv * inv * inv) : 0.0f;
-          if (in && r < dij) {
-            // overlapping pair: clamped Coulomb minus the erf field, exactly
-            const float gg = c2 * expf(-a * a * r2) / r;
-            f = s.q * (1.0f / (dij * dij) - (erff(a * r) / r2 - gg)) / r;
+          const float u = fminf(r * tq, (float)kSrTable);   // u >= kSrTable: beyond r_max, entry (0, 0)
+          const float2 tv = tab[(int)u];
+          float f = s.q * fmaf(__builtin_amdgcn_fractf(u), tv.y, tv.x) * ((inv * inv) * inv);
+          if (__builtin_amdgcn_ballot_w64(r2 < near2q)) {
+            // a pair of this source may overlap: clamped Coulomb minus the erf field, exactly
+            const float dij = me.d + s.d;
+            if (r2 > 1e-20f && r < dij) {
+              const float gg = c2q * expf(-aq * aq * r2) / r;
+              f = s.q * (1.0f / (dij * dij) - (erff(aq * r) / r2 - gg)) / r;
+            }
           }
+          sx = fmaf(f, dx, sx);
+          sy = fmaf(f, dy, sy);
+          sz = fmaf(f, dz, sz);
         } else {
-          f = 0.0;
-          if (in) {
+          const Real dx = Real((SPos)(me.x - s.x)) * ux;
+          const Real dy = Real((SPos)me.y - (SPos)s.y) * ur;
+          const Real dz = Real((SPos)me.z - (SPos)s.z) * ur;
+          const Real r2 = dx * dx + dy * dy + dz * dz;
+          const Real dij = Real(0.5) * (me.d + s.d);
+          Real f = 0.0;
+          if (r2 < rmax2 && r2 > Real(0)) {
             const double r = sqrt(r2);
             const double gg = c2 * exp(-a * a * r2) / r;
             f = (r >= dij ? erfc(a * r) / r2 + gg : 1.0 / (dij * dij) - (erf(a * r) / r2 - gg)) * s.q / r;
           }
+          sx += f * dx;
+          sy += f * dy;
+          sz += f * dz;
         }
-        sx += f * dx;
-        sy += f * dy;
-        sz += f * dz;
       }
     }
     part[w][0][lane] = sx;
@@ -449,9 +494,11 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
       }
       const int i = sorted[t0 + kt];
       const double u2 = ph.ux * ph.ux;
-      st.cx[i] = Real((slong[i] + ax) * u2);
-      st.cy[i] = Real((slong[ph.N + i] + ay) * u2);
-      st.cz[i] = Real((slong[2 * (int64_t)ph.N + i] + az) * u2);
+      // the FP32 sums are in y/z quanta: (u_x / u_r)^2 takes them to x quanta, like slong * u_x^2
+      const double us = sizeof(Real) == 4 ? (ph.ux / ph.ur) * (ph.ux / ph.ur) : u2;
+      st.cx[i] = Real(slong[i] * u2 + ax * us);
+      st.cy[i] = Real(slong[ph.N + i] * u2 + ay * us);
+      st.cz[i] = Real(slong[2 * (int64_t)ph.N + i] * u2 + az * us);
     }
     __syncthreads();
   }
@@ -467,15 +514,16 @@ int ilog2(int n) {
 void fft3d(const P3mDev &m, double2 *d, int sign, hipStream_t s) {
   const int64_t P = m.P, nx = m.nx;
   const int64_t total = nx * P * P;
+  const int lp = ilog2((int)P);
   // z: points contiguous, line l at l * P
-  hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)(total / kFftLds)), dim3(256), 0, s, d, (int)P, ilog2((int)P),
-                     (int64_t)1, (int64_t)0, P, (int64_t)1, sign, 1);
+  hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)(total / kFftLds)), dim3(256), 0, s, d, lp, 0, (int64_t)0, P,
+                     (int64_t)1, sign, 1);
   // y: line (ix, iz) at ix P^2 + iz, points P apart
-  hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)(total / kFftLds)), dim3(256), 0, s, d, (int)P, ilog2((int)P), P,
-                     (int64_t)1, P * P, P, sign, 0);
+  hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)(total / kFftLds)), dim3(256), 0, s, d, lp, lp, (int64_t)1, P * P,
+                     P, sign, 0);
   // x: line (iy, iz) at iy P + iz, points P^2 apart
-  hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)(total / kFftLds)), dim3(256), 0, s, d, (int)nx, ilog2((int)nx),
-                     (int64_t)1, (int64_t)0, (int64_t)1, P * P, sign, 0);
+  hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)(total / kFftLds)), dim3(256), 0, s, d, ilog2((int)nx), 0,
+                     (int64_t)0, (int64_t)1, P * P, sign, 0);
 }
 
 }  // namespace
@@ -486,28 +534,28 @@ void p3m_setup_green(const P3mDev &m, double L, int images, hipStream_t s) {
   hipLaunchKernelGGL(k_p3m_green, dim3(g), dim3(256), 0, s, m, L, images, m.ghat[0], m.ghat[1], m.ghat[2]);
   for (int c = 0; c < 3; ++c) fft3d(m, m.ghat[c], -1, s);
   hipLaunchKernelGGL(k_p3m_deconv, dim3(g), dim3(256), 0, s, m, m.ghat[0], m.ghat[1], m.ghat[2]);
-  hipLaunchKernelGGL(k_p3m_table, dim3((kSrTable + 255) / 256), dim3(256), 0, s, m, m.table);
+  hipLaunchKernelGGL(k_p3m_table, dim3((kSrTable + 256) / 256), dim3(256), 0, s, m, m.table);
 }
 
 template <class Real> void launch_p3m(const State<Real> &st, const Phys &ph, const P3mDev &m, hipStream_t s) {
   if (ph.N <= 0) return;
   const int64_t total = (int64_t)m.nx * m.P * m.P;
   const unsigned gm = (unsigned)((total + 255) / 256), gp = (unsigned)((ph.N + 255) / 256);
-  hipLaunchKernelGGL((k_p3m_assign<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.qmesh);
+  // short-range cells first: the mesh passes also walk the particles in cell order
+  const int ncell = m.ncx * m.ncy * m.ncy;
+  hipLaunchKernelGGL((k_p3m_bin<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.cell_of, m.counts);
+  hipLaunchKernelGGL(k_p3m_scan, dim3(1), dim3(1024), 0, s, ncell, m.counts, m.starts, m.fill);
+  hipLaunchKernelGGL(k_p3m_scatter, dim3(gp), dim3(256), 0, s, ph.N, m.cell_of, m.fill, m.sorted);
+  hipLaunchKernelGGL(k_p3m_sort, dim3((unsigned)ncell), dim3(256), 0, s, ncell, m.starts, m.sorted, m.counts);
+  hipLaunchKernelGGL((k_p3m_assign<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.sorted, m.qmesh);
   hipLaunchKernelGGL(k_p3m_load, dim3(gm), dim3(256), 0, s, m, m.qmesh, m.rho);
   fft3d(m, m.rho, -1, s);
   for (int c = 0; c < 3; ++c) {
     hipLaunchKernelGGL(k_p3m_mul, dim3(gm), dim3(256), 0, s, m, m.rho, m.ghat[c], m.work);
     fft3d(m, m.work, +1, s);
-    hipLaunchKernelGGL((k_p3m_interp<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.work,
+    hipLaunchKernelGGL((k_p3m_interp<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.sorted, m.work,
                        m.slong + (int64_t)c * ph.N);
   }
-  const int ncell = m.ncx * m.ncy * m.ncy;
-  hipLaunchKernelGGL((k_p3m_bin<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.cell_of, m.counts);
-  hipLaunchKernelGGL(k_p3m_scan, dim3(1), dim3(1024), 0, s, ncell, m.counts, m.starts, m.fill);
-  hipLaunchKernelGGL(k_p3m_scatter, dim3(gp), dim3(256), 0, s, ph.N, m.cell_of, m.fill, m.sorted);
-  hipLaunchKernelGGL(k_p3m_sort, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, ncell, m.starts, m.sorted,
-                     m.counts);
   SrRec<Real> *rec = (SrRec<Real> *)m.rec;
   hipLaunchKernelGGL((k_p3m_records<Real>), dim3(gp), dim3(256), 0, s, st, ph, m.sorted, rec);
   hipLaunchKernelGGL((k_p3m_short<Real>), dim3(ncell), dim3(64 * kSrWaves), 0, s, st, ph, m, m.starts, m.sorted, rec,
