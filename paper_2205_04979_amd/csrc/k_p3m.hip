@@ -352,7 +352,8 @@ __global__ void k_p3m_records(State<Real> st, Phys ph, const int32_t *__restrict
   rec[k] = r;
 }
 
-constexpr int kSrLds = 65536;    // bytes of LDS for staged neighbour records
+constexpr int kSrLds = 65536;    // bytes of LDS for staged neighbour records (FP64 form)
+constexpr int kSrLdsF32 = 45056; // the same for the FP32 form, which also holds the profile table
 constexpr int kSrWaves = 4;      // waves per cell: each takes every 4th staged source
 constexpr int kSrTable = 4096;   // intervals of the tabulated short-range profile (FP32 form)
 
@@ -376,8 +377,9 @@ __global__ void k_p3m_table(P3mDev m, float2 *__restrict__ tab) {
 // closer than r_max, added to the long-range part; result in units of the x quantum.  One
 // workgroup per cell: the records of the 27 neighbouring cells are staged in LDS (in chunks when
 // they exceed it); the cell's targets take one lane each in every wave, and the waves split the
-// staged sources, combined in LDS in a fixed order.  FP32: branch-free tabulated profile
-// (overlapping pairs, which are rare, take the exact clamp); FP64: the exact expressions.
+// staged sources, combined in LDS in a fixed order.  FP32: branch-free tabulated profile read from
+// a copy of the table in LDS, in y/z position quanta (overlapping pairs, which are rare, take the
+// exact clamp); FP64: the exact expressions, in metres.
 template <class Real>
 __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phys ph, P3mDev m,
                                                              const int32_t *__restrict__ starts,
@@ -387,14 +389,18 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
                                                              const float2 *__restrict__ tab) {
   using Pos = typename Prec<Real>::Pos;
   using SPos = typename std::make_signed<Pos>::type;
-  constexpr int CAP = kSrLds / sizeof(SrRec<Real>);
+  // FP32: 44 KB of staged records + the 32 KB profile table in LDS (two workgroups per CU)
+  constexpr int CAP = (sizeof(Real) == 4 ? kSrLdsF32 : kSrLds) / sizeof(SrRec<Real>);
   __shared__ SrRec<Real> src[CAP];
+  __shared__ float2 stab[sizeof(Real) == 4 ? kSrTable + 1 : 1];
   __shared__ Real part[kSrWaves][3][64];
   __shared__ int32_t rb[27], rn[27], roff[28];
   const int c = blockIdx.x;
   const int cz = c % m.ncy, cy = (c / m.ncy) % m.ncy, cx = c / (m.ncy * m.ncy);
   const int t0 = starts[c], nt = starts[c + 1] - t0;
   if (nt == 0) return;   // uniform: the whole workgroup leaves
+  if constexpr (sizeof(Real) == 4)   // read after the barriers below
+    for (int k = threadIdx.x; k <= kSrTable; k += 64 * kSrWaves) stab[k] = tab[k];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (threadIdx.x < 27) {
     const int ox = (int)threadIdx.x / 9 - 1, oy = ((int)threadIdx.x / 3) % 3 - 1, oz = (int)threadIdx.x % 3 - 1;
@@ -438,6 +444,7 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
         for (int g = lo + (int)threadIdx.x; g < hi; g += 64 * kSrWaves) src[g - cb] = rec[rb[k] + (g - roff[k])];
       }
       __syncthreads();
+#pragma unroll 4
       for (int e = w; e < n; e += kSrWaves) {
         const SrRec<Real> s = src[e];
         if constexpr (sizeof(Real) == 4) {
@@ -449,7 +456,7 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
           const float inv = __builtin_amdgcn_rsqf(r2);
           const float r = r2 * inv;
           const float u = fminf(r * tq, (float)kSrTable);   // u >= kSrTable: beyond r_max, entry (0, 0)
-          const float2 tv = tab[(int)u];
+          const float2 tv = stab[(int)u];
           float f = s.q * fmaf(__builtin_amdgcn_fractf(u), tv.y, tv.x) * ((inv * inv) * inv);
           if (__builtin_amdgcn_ballot_w64(r2 < near2q)) {
             // a pair of this source may overlap: clamped Coulomb minus the erf field, exactly
