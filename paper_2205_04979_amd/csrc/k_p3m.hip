@@ -135,7 +135,33 @@ __global__ __launch_bounds__(256) void k_fft_lines(double2 *__restrict__ data, i
     buf[(line << log2n) + rev] = data[addr(line, p)];
   }
   __syncthreads();
-  for (int lg = 1; lg <= log2n; ++lg) {
+  // radix-2 stages lg and lg + 1 fused: each group of 4 points (i0, i0 + h, i0 + 2h, i0 + 3h),
+  // h = 2^(lg-1), takes both stages' butterflies in registers -- the same operations in the
+  // same order as two separate stages, with one LDS round trip and one barrier instead of two
+  int lg = 1;
+  for (; lg + 1 <= log2n; lg += 2) {
+    const int half = 1 << (lg - 1);
+    for (int b = threadIdx.x; b < kFftLds / 4; b += blockDim.x) {
+      const int line = b >> (log2n - 2), k = b & ((n >> 2) - 1);
+      const int pos = k & (half - 1);
+      const int i0 = (line << log2n) + ((k >> (lg - 1)) << (lg + 1)) + pos;
+      const double2 w1 = tw[pos << (log2n - lg)];
+      const double2 w2a = tw[pos << (log2n - lg - 1)], w2b = tw[(pos + half) << (log2n - lg - 1)];
+      const double2 a0 = buf[i0], a1 = buf[i0 + half], a2 = buf[i0 + 2 * half], a3 = buf[i0 + 3 * half];
+      double2 v = cmul(w1, a1);
+      const double2 b0 = make_double2(a0.x + v.x, a0.y + v.y), b1 = make_double2(a0.x - v.x, a0.y - v.y);
+      v = cmul(w1, a3);
+      const double2 b2 = make_double2(a2.x + v.x, a2.y + v.y), b3 = make_double2(a2.x - v.x, a2.y - v.y);
+      v = cmul(w2a, b2);
+      buf[i0] = make_double2(b0.x + v.x, b0.y + v.y);
+      buf[i0 + 2 * half] = make_double2(b0.x - v.x, b0.y - v.y);
+      v = cmul(w2b, b3);
+      buf[i0 + half] = make_double2(b1.x + v.x, b1.y + v.y);
+      buf[i0 + 3 * half] = make_double2(b1.x - v.x, b1.y - v.y);
+    }
+    __syncthreads();
+  }
+  if (lg == log2n) {   // odd log2n: the last radix-2 stage
     const int half = 1 << (lg - 1);
     for (int b = threadIdx.x; b < kFftLds / 2; b += blockDim.x) {
       const int line = b >> (log2n - 1), k = b & ((n >> 1) - 1);
@@ -353,8 +379,8 @@ __global__ void k_p3m_records(State<Real> st, Phys ph, const int32_t *__restrict
 }
 
 constexpr int kSrLds = 65536;    // bytes of LDS for staged neighbour records (FP64 form)
-constexpr int kSrLdsF32 = 45056; // the same for the FP32 form, which also holds the profile table
-constexpr int kSrWaves = 4;      // waves per cell: each takes every 4th staged source
+constexpr int kSrLdsF32 = 40960; // the same for the FP32 form, which also holds the profile table
+constexpr int kSrWaves = 8;      // waves per cell: each takes every 8th staged source
 constexpr int kSrTable = 4096;   // intervals of the tabulated short-range profile (FP32 form)
 
 // Short-range force profile g(s) = erfc(s) + (2 s / sqrt(pi)) exp(-s^2), s = alpha r, so that the
@@ -389,7 +415,7 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
                                                              const float2 *__restrict__ tab) {
   using Pos = typename Prec<Real>::Pos;
   using SPos = typename std::make_signed<Pos>::type;
-  // FP32: 44 KB of staged records + the 32 KB profile table in LDS (two workgroups per CU)
+  // FP32: 40 KB of staged records + the 32 KB profile table in LDS (two workgroups per CU)
   constexpr int CAP = (sizeof(Real) == 4 ? kSrLdsF32 : kSrLds) / sizeof(SrRec<Real>);
   __shared__ SrRec<Real> src[CAP];
   __shared__ float2 stab[sizeof(Real) == 4 ? kSrTable + 1 : 1];
@@ -430,6 +456,7 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
   const float kx = (float)(ph.ux / ph.ur), aq = (float)(m.alpha * ph.ur), c2q = (float)(2.0 * m.alpha * ph.ur / sqrt(M_PI));
   const float tq = (float)(kSrTable * ph.ur / m.rmax);
   const float near2q = (float)(ph.near2 * (ph.ux / ph.ur) * (ph.ux / ph.ur));
+  const bool once = total <= CAP;   // all sources fit: staged once for every target block
   for (int tb = 0; tb < nt; tb += 64) {
     const int kt = tb + lane;
     const bool has = kt < nt;
@@ -437,13 +464,15 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
     Real sx = 0, sy = 0, sz = 0;
     for (int cb = 0; cb < total; cb += CAP) {
       const int n = min(CAP, total - cb);
-      __syncthreads();
-      // staged entries [cb, cb + n) of the concatenated 27 cell ranges, cell by cell
-      for (int k = 0; k < 27; ++k) {
-        const int lo = max(roff[k], cb), hi = min(roff[k + 1], cb + n);
-        for (int g = lo + (int)threadIdx.x; g < hi; g += 64 * kSrWaves) src[g - cb] = rec[rb[k] + (g - roff[k])];
+      if (!once || tb == 0) {
+        __syncthreads();
+        // staged entries [cb, cb + n) of the concatenated 27 cell ranges, cell by cell
+        for (int k = 0; k < 27; ++k) {
+          const int lo = max(roff[k], cb), hi = min(roff[k + 1], cb + n);
+          for (int g = lo + (int)threadIdx.x; g < hi; g += 64 * kSrWaves) src[g - cb] = rec[rb[k] + (g - roff[k])];
+        }
+        __syncthreads();
       }
-      __syncthreads();
 #pragma unroll 4
       for (int e = w; e < n; e += kSrWaves) {
         const SrRec<Real> s = src[e];
