@@ -181,34 +181,105 @@ __global__ __launch_bounds__(256) void k_fft_lines(double2 *__restrict__ data, i
   }
 }
 
-// TSC charge assignment in 64-bit fixed point (units of the per-sample bound 2^-62 sum |q~|).
+// TSC stencil of particle i: centre node (ix unwrapped in [0, nx], iy and iz clamped to
+// [1, nc - 2]) and weights; false for a particle without charge.
 template <class Real>
-__global__ void k_p3m_assign(State<Real> st, Phys ph, P3mDev m, const int32_t *__restrict__ order,
-                             unsigned long long *__restrict__ qmesh) {
-  // particles taken in short-range cell order, so neighbouring lanes add to nearby nodes (the
-  // integer additions commute: the order does not change the result)
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= ph.N) return;
-  const int i = order[k];
-  const double q = (double)st.js[i].q;
-  if (q == 0.0) return;
-  const double qs = *m.q_scale;
-  double gx, gy, gz, wx[3], wy[3], wz[3];
-  int ix, iy, iz;
+__device__ __forceinline__ bool tsc_stencil(const State<Real> &st, const Phys &ph, const P3mDev &m, int i, int &ix,
+                                            int &iy, int &iz, double (&wx)[3], double (&wy)[3], double (&wz)[3]) {
+  if (st.js[i].q == 0) return false;
+  double gx, gy, gz;
   mesh_coords<Real>(st, ph, m, i, gx, gy, gz);
   tsc(gx, ix, wx);
   tsc(gy, iy, wy);
   tsc(gz, iz, wz);
   iy = min(max(iy, 1), m.nc - 2);   // suspended particles stay inside [-R, R]; the clamp only guards
   iz = min(max(iz, 1), m.nc - 2);
-  for (int a = 0; a < 3; ++a) {
-    int jx = ix + a - 1;
-    jx = jx < 0 ? jx + m.nx : (jx >= m.nx ? jx - m.nx : jx);
-    for (int b = 0; b < 3; ++b)
-      for (int c = 0; c < 3; ++c) {
-        const int64_t o = ((int64_t)jx * m.nc + (iy + b - 1)) * m.nc + (iz + c - 1);
-        atomicAdd(qmesh + o, (unsigned long long)__double2ll_rn(q * wx[a] * wy[b] * wz[c] * qs));
+  return true;
+}
+
+// Fixed-point contribution of a particle to stencil node (a, b, c), units of the per-sample
+// bound 2^-62 sum |q~|.
+__device__ __forceinline__ unsigned long long tsc_part(double q, const double (&wx)[3], const double (&wy)[3],
+                                                       const double (&wz)[3], int a, int b, int c, double qs) {
+  return (unsigned long long)__double2ll_rn(q * wx[a] * wy[b] * wz[c] * qs);
+}
+
+constexpr int kAsgCap = 4096;   // mesh nodes of the per-cell accumulation box (32 KB of LDS)
+
+// TSC charge assignment in 64-bit fixed point, one workgroup per short-range cell: the cell's
+// particles add their 27 stencil contributions to an LDS box spanning the cell's stencils (LDS
+// atomics), and the box is added to the mesh with one global atomic per touched node.  Integer
+// additions commute, so the mesh is the same as with per-particle global atomics, which a cell
+// whose box exceeds kAsgCap nodes uses instead.
+template <class Real>
+__global__ __launch_bounds__(256) void k_p3m_assign(State<Real> st, Phys ph, P3mDev m,
+                                                    const int32_t *__restrict__ starts,
+                                                    const int32_t *__restrict__ sorted,
+                                                    unsigned long long *__restrict__ qmesh) {
+  __shared__ unsigned long long box[kAsgCap];
+  __shared__ int lo[3], hi[3];
+  const int cell = blockIdx.x;
+  const int b0 = starts[cell], n = starts[cell + 1] - b0;
+  if (n == 0) return;   // uniform
+  const double qs = *m.q_scale;
+  if (threadIdx.x < 3) {
+    lo[threadIdx.x] = INT_MAX;
+    hi[threadIdx.x] = INT_MIN;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    int ix, iy, iz;
+    double wx[3], wy[3], wz[3];
+    if (!tsc_stencil<Real>(st, ph, m, sorted[b0 + k], ix, iy, iz, wx, wy, wz)) continue;
+    atomicMin(&lo[0], ix); atomicMax(&hi[0], ix);
+    atomicMin(&lo[1], iy); atomicMax(&hi[1], iy);
+    atomicMin(&lo[2], iz); atomicMax(&hi[2], iz);
+  }
+  __syncthreads();
+  if (lo[0] > hi[0]) return;   // uniform: no charged particle
+  const int ex = hi[0] - lo[0] + 3, ey = hi[1] - lo[1] + 3, ez = hi[2] - lo[2] + 3;
+  const int64_t vol = (int64_t)ex * ey * ez;
+  if (vol > kAsgCap) {   // uniform: per-particle global atomics
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+      const int i = sorted[b0 + k];
+      int ix, iy, iz;
+      double wx[3], wy[3], wz[3];
+      if (!tsc_stencil<Real>(st, ph, m, i, ix, iy, iz, wx, wy, wz)) continue;
+      const double q = (double)st.js[i].q;
+      for (int a = 0; a < 3; ++a) {
+        int jx = ix + a - 1;
+        jx = jx < 0 ? jx + m.nx : (jx >= m.nx ? jx - m.nx : jx);
+        for (int b = 0; b < 3; ++b)
+          for (int c = 0; c < 3; ++c)
+            atomicAdd(qmesh + ((int64_t)jx * m.nc + (iy + b - 1)) * m.nc + (iz + c - 1),
+                      tsc_part(q, wx, wy, wz, a, b, c, qs));
       }
+    }
+    return;
+  }
+  for (int e = threadIdx.x; e < vol; e += blockDim.x) box[e] = 0ull;
+  __syncthreads();
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const int i = sorted[b0 + k];
+    int ix, iy, iz;
+    double wx[3], wy[3], wz[3];
+    if (!tsc_stencil<Real>(st, ph, m, i, ix, iy, iz, wx, wy, wz)) continue;
+    const double q = (double)st.js[i].q;
+    // box coordinates of the stencil's first node: (ix - 1 - (lo - 1), ...) = (ix - lo, ...)
+    const int bx = ix - lo[0], by = iy - lo[1], bz = iz - lo[2];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        for (int c = 0; c < 3; ++c)
+          atomicAdd(&box[((bx + a) * ey + (by + b)) * ez + (bz + c)], tsc_part(q, wx, wy, wz, a, b, c, qs));
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < vol; e += blockDim.x) {
+    const unsigned long long v = box[e];
+    if (v == 0ull) continue;
+    const int c = e % ez, b = (e / ez) % ey, a = e / (ey * ez);
+    int jx = lo[0] - 1 + a;
+    jx = jx < 0 ? jx + m.nx : (jx >= m.nx ? jx - m.nx : jx);
+    atomicAdd(qmesh + ((int64_t)jx * m.nc + (lo[1] - 1 + b)) * m.nc + (lo[2] - 1 + c), v);
   }
 }
 
@@ -583,7 +654,8 @@ template <class Real> void launch_p3m(const State<Real> &st, const Phys &ph, con
   hipLaunchKernelGGL(k_p3m_scan, dim3(1), dim3(1024), 0, s, ncell, m.counts, m.starts, m.fill);
   hipLaunchKernelGGL(k_p3m_scatter, dim3(gp), dim3(256), 0, s, ph.N, m.cell_of, m.fill, m.sorted);
   hipLaunchKernelGGL(k_p3m_sort, dim3((unsigned)ncell), dim3(256), 0, s, ncell, m.starts, m.sorted, m.counts);
-  hipLaunchKernelGGL((k_p3m_assign<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.sorted, m.qmesh);
+  hipLaunchKernelGGL((k_p3m_assign<Real>), dim3((unsigned)ncell), dim3(256), 0, s, st, ph, m, m.starts, m.sorted,
+                     m.qmesh);
   hipLaunchKernelGGL(k_p3m_load, dim3(gm), dim3(256), 0, s, m, m.qmesh, m.rho);
   fft3d(m, m.rho, -1, s);
   for (int c = 0; c < 3; ++c) {
