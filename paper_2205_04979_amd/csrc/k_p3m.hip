@@ -305,10 +305,23 @@ __global__ void k_p3m_mul(P3mDev m, const double2 *__restrict__ a, const double2
   out[e] = cmul(a[e], g[e]);
 }
 
-// TSC interpolation of one field component (real part of the unnormalised inverse transform).
+// Two real fields in one transform: out = a g1 + i a g2.  The charge and both Green's functions
+// are real on the mesh, so the inverse transform of a g1 and of a g2 are real, and the inverse
+// transform of out is E1 + i E2.
+__global__ void k_p3m_mul2(P3mDev m, const double2 *__restrict__ a, const double2 *__restrict__ g1,
+                           const double2 *__restrict__ g2, double2 *__restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m.nx * m.P * m.P) return;
+  const double2 p = cmul(a[e], g1[e]), q = cmul(a[e], g2[e]);
+  out[e] = make_double2(p.x - q.y, p.y + q.x);
+}
+
+// TSC interpolation of the unnormalised inverse transform: its real part to out_re and, when
+// out_im is given, its imaginary part (a second real field) to out_im.
 template <class Real>
 __global__ void k_p3m_interp(State<Real> st, Phys ph, P3mDev m, const int32_t *__restrict__ order,
-                             const double2 *__restrict__ E, double *__restrict__ out) {
+                             const double2 *__restrict__ E, double *__restrict__ out_re,
+                             double *__restrict__ out_im) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;   // cell order, for locality of the mesh reads
   if (k >= ph.N) return;
   const int i = order[k];
@@ -320,15 +333,21 @@ __global__ void k_p3m_interp(State<Real> st, Phys ph, P3mDev m, const int32_t *_
   tsc(gz, iz, wz);
   iy = min(max(iy, 1), m.nc - 2);
   iz = min(max(iz, 1), m.nc - 2);
-  double s = 0.0;
+  double s = 0.0, t = 0.0;
   for (int a = 0; a < 3; ++a) {
     int jx = ix + a - 1;
     jx = jx < 0 ? jx + m.nx : (jx >= m.nx ? jx - m.nx : jx);
     for (int b = 0; b < 3; ++b)
-      for (int c = 0; c < 3; ++c)
-        s += wx[a] * wy[b] * wz[c] * E[((int64_t)jx * m.P + (iy + b - 1)) * m.P + (iz + c - 1)].x;
+      for (int c = 0; c < 3; ++c) {
+        const double w = wx[a] * wy[b] * wz[c];
+        const double2 v = E[((int64_t)jx * m.P + (iy + b - 1)) * m.P + (iz + c - 1)];
+        s += w * v.x;
+        t += w * v.y;
+      }
   }
-  out[i] = s / ((double)m.nx * m.P * m.P);
+  const double norm = 1.0 / ((double)m.nx * m.P * m.P);
+  out_re[i] = s * norm;
+  if (out_im) out_im[i] = t * norm;
 }
 
 // Short-range cell of a particle (cells of at least r_max; x periodic).
@@ -658,12 +677,15 @@ template <class Real> void launch_p3m(const State<Real> &st, const Phys &ph, con
                      m.qmesh);
   hipLaunchKernelGGL(k_p3m_load, dim3(gm), dim3(256), 0, s, m, m.qmesh, m.rho);
   fft3d(m, m.rho, -1, s);
-  for (int c = 0; c < 3; ++c) {
-    hipLaunchKernelGGL(k_p3m_mul, dim3(gm), dim3(256), 0, s, m, m.rho, m.ghat[c], m.work);
-    fft3d(m, m.work, +1, s);
-    hipLaunchKernelGGL((k_p3m_interp<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.sorted, m.work,
-                       m.slong + (int64_t)c * ph.N);
-  }
+  // E_x + i E_y from one inverse transform, then E_z
+  hipLaunchKernelGGL(k_p3m_mul2, dim3(gm), dim3(256), 0, s, m, m.rho, m.ghat[0], m.ghat[1], m.work);
+  fft3d(m, m.work, +1, s);
+  hipLaunchKernelGGL((k_p3m_interp<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.sorted, m.work, m.slong,
+                     m.slong + ph.N);
+  hipLaunchKernelGGL(k_p3m_mul, dim3(gm), dim3(256), 0, s, m, m.rho, m.ghat[2], m.work);
+  fft3d(m, m.work, +1, s);
+  hipLaunchKernelGGL((k_p3m_interp<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.sorted, m.work,
+                     m.slong + 2 * (int64_t)ph.N, (double *)nullptr);
   SrRec<Real> *rec = (SrRec<Real> *)m.rec;
   hipLaunchKernelGGL((k_p3m_records<Real>), dim3(gp), dim3(256), 0, s, st, ph, m.sorted, rec);
   hipLaunchKernelGGL((k_p3m_short<Real>), dim3(ncell), dim3(64 * kSrWaves), 0, s, st, ph, m, m.starts, m.sorted, rec,
