@@ -75,6 +75,42 @@ def gpu_sim(p, f, off, real_bytes):
     return sim
 
 
+def test_fp64_adjoint_single_particle_image_force_closed_form():
+    """One particle, the wall image force only (no drag, pair or cohesion forces), one step of the
+    smoothed tally: with a0 = k_e s^2 qb^2 / (4 h0^2 m) radially outward and v0 = 0, the step moves the
+    particle to rho1 = rho0 + dt^2 a0 / 2 and J = m (1 - exp(-l1)), l1 = sigma(z1) / tau_s,
+    z1 = -(R - rho1 - d/2) / (eps d).  So dJ/ds = m exp(-l1) sigma'(z1) / tau_s * dt^2 a0 / (s eps d)
+    (the image force is proportional to s^2), dJ/dA = 0 (no cohesion term) and dJ/dT = 0."""
+    from oracle.physics import coulomb_constant, particle_mass
+    from paper_2205_04979_amd.depo import Simulation
+    p = physical_params(180.0, soft_tally=True, drag=False, collide=False, vdw=False, wall_vdw=False,
+                        coulomb=False, rebound_osu=False, dt=1e-5)
+    R, L = p["R"], p["L"]
+    d, qb, s = 10e-6, 1e-14, 0.7
+    rho0 = R - 0.5 * d - 1e-6
+    x = np.array([[0.5 * L, rho0, 0.0]])
+    f = make_workload("plain-1k", n=4, field_n=16).field()
+    sp = np.array([[s, 3e-19, 300.0]])
+    say("case: adjoint closed form, single particle, image force")
+    sim = Simulation(p, np.array([0, 1]), f.shape[:3], real_bytes=8)
+    sim.init_field(f)
+    sim.seed(sp, x, np.array([d]), np.array([qb]), v=np.zeros((1, 3)))
+    g = sim.adjoint(1, 1)[0]
+    m = particle_mass(d, p["rho_p"])
+    h0 = R - rho0
+    a0 = coulomb_constant(p["eps0"]) * (s * qb) ** 2 / (4.0 * h0 * h0 * m)
+    dt, eps, tau = p["dt"], p["soft_eps"], p["soft_tau"]
+    rho1 = rho0 + 0.5 * dt * dt * a0
+    z1 = -(R - rho1 - 0.5 * d) / (eps * d)
+    sig = 1.0 / (1.0 + np.exp(-z1))
+    l1 = sig / tau
+    dJ_ds = m * np.exp(-l1) * sig * (1.0 - sig) / tau * dt * dt * a0 / (s * eps * d)
+    say("adjoint", g.tolist(), "closed form", dJ_ds)
+    assert 0.1 < sig < 0.9                      # the step lands where the smoothed tally is sensitive
+    assert g[0] == pytest.approx(dJ_ds, rel=1e-8)
+    assert g[1] == 0.0 and g[2] == 0.0
+
+
 def test_fp64_adjoint_matches_oracle_finite_differences():
     """The cohesion cutoff (a jump of 0.27 A/d at gap d/4) makes J piecewise smooth; the adjoint
     differentiates the smooth branch, so the seeded case is one where no cutoff crossing falls inside
