@@ -28,8 +28,13 @@ def _key(sim) -> str:
     return f"{name}|fp{8 * sim.real_bytes}|S={sim.s}|N={sim.n}"
 
 
-def autotune(sim, steps: int = 3, cache_path: Optional[str] = None, verbose: bool = False):
-    """Return (best_shape, {shape: ms per Coulomb launch}) and apply the best shape to ``sim``."""
+def autotune(sim, steps: int = 3, cache_path: Optional[str] = None, verbose: bool = False, refine: int = 3,
+             rounds: int = 3):
+    """Return (best_shape, {shape: ms per Coulomb launch}) and apply the best shape to ``sim``.
+
+    Every shape is timed over ``steps`` steps; the ``refine`` fastest are then timed again in
+    ``rounds`` round-robin passes (so that clock drift affects them alike) and each keeps its
+    fastest measurement."""
     key = _key(sim)
     cache = {}
     if cache_path and os.path.exists(cache_path):
@@ -56,7 +61,14 @@ def autotune(sim, steps: int = 3, cache_path: Optional[str] = None, verbose: boo
         times[shp] = ms
         if verbose:
             print(f"[autotune] shape {shp}: {ms:.4f} ms per pair-kernel launch", flush=True)
-    best = min(times, key=times.get)
+    finalists = sorted(times, key=times.get)[:max(1, refine)]
+    for _ in range(rounds if len(finalists) > 1 else 0):
+        for shp in finalists:
+            sim.set_kernel_config(*shp)
+            ms = sim.step_timed(steps)["coulomb"] / steps
+            sim.state_upload(blob)
+            times[shp] = min(times[shp], ms)
+    best = min(finalists, key=times.get)
     sim.set_kernel_config(*best)
     if cache_path:
         cache[key] = {"best": list(best), "ms": {json.dumps(list(k)): v for k, v in times.items()}}
