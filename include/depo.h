@@ -137,7 +137,7 @@ const char *depo_status_string(int status);
 /* Create a context from validated parameters.  Host only, touches no GPU.
  * Returns DEPO_E_INVALID (with *out = NULL) for non-positive or non-finite
  * lengths, densities, viscosity or dt, e_pp outside (0, 1], tau_col_steps < 1,
- * real_bytes not 4 or 8, L < 2R, unknown flag bits, reserved != 0 or a negative or
+ * real_bytes not 4 or 8, unknown flag bits, reserved != 0 or a negative or
  * non-finite u_bulk. */
 depo_status depo_create(const depo_params *p, depo_ctx **out);
 
