@@ -269,7 +269,10 @@ depo_status depo_state_upload(depo_ctx *ctx, const void *h_blob, size_t bytes, d
 /* Device bytes needed by depo_adjoint for n_steps and a checkpoint interval
  * (1 <= ckpt_every <= n_steps): ceil(n_steps / ckpt_every) stored states, the
  * ckpt_every - 1 per-step states of one segment (its last state is the next
- * checkpoint), the final state and the adjoint arrays.  Host only. */
+ * checkpoint), the final state, the adjoint arrays and, with Coulomb on, the
+ * raw pair sums (3 reals per particle) of the n_steps - ceil(n_steps /
+ * ckpt_every) steps the reverse sweep recomputes, so that it does not rerun
+ * the O(N^2) pair kernel.  Host only. */
 depo_status depo_adjoint_workspace_bytes(const depo_ctx *ctx, int32_t n_steps, int32_t ckpt_every, size_t *bytes);
 
 /* Gradient of J = sum_s w_s J_s, J_s = sum_{i in s} m_i (1 - exp(-l_i)) the

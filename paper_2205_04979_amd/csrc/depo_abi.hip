@@ -796,10 +796,13 @@ template <class Real> struct AdjPlan {
   std::vector<TapeEntry<Real>> ckpt, tape;
   TapeEntry<Real> fin{};
   AdjState<Real> ad{};
+  // raw Coulomb sums [n_steps - n_ckpt][3][N] of the steps the reverse sweep recomputes (Coulomb
+  // on): step c*seg_len + j of segment c, j < seg_len - 1, sits at entry c*(seg_len - 1) + j
+  Real *ctape = nullptr;
 };
 
 template <class Real>
-size_t carve_adjoint(const depo_ctx *ctx, char *base, int n_ckpt, int seg_len, AdjPlan<Real> &pl) {
+size_t carve_adjoint(const depo_ctx *ctx, char *base, int n_steps, int n_ckpt, int seg_len, AdjPlan<Real> &pl) {
   using Pos = typename Prec<Real>::Pos;
   const size_t N = (size_t)std::max<int64_t>(ctx->N, 1);
   size_t o = 0;
@@ -834,6 +837,8 @@ size_t carve_adjoint(const depo_ctx *ctx, char *base, int n_ckpt, int seg_len, A
   a.rec = (JAdj<Real> *)take(N * sizeof(JAdj<Real>));
   a.weights = (double *)take((size_t)ctx->S * 8);
   a.out = (double *)take((size_t)ctx->S * 2 * 8);
+  const size_t n_sums = (size_t)(n_steps - n_ckpt);
+  pl.ctape = (ctx->p.flags & DEPO_COULOMB) && n_sums ? (Real *)take(n_sums * 3 * N * sizeof(Real)) : nullptr;
   return o;
 }
 
@@ -842,9 +847,9 @@ depo_status do_adjoint(depo_ctx *ctx, int n, int ce, const double *hw, double *h
                        hipStream_t s) {
   AdjPlan<Real> pl;
   const int K = (n + ce - 1) / ce;
-  const size_t need = carve_adjoint<Real>(ctx, nullptr, K, ce, pl);
+  const size_t need = carve_adjoint<Real>(ctx, nullptr, n, K, ce, pl);
   if (bytes < need) return ctx->fail(DEPO_E_CAPACITY, "adjoint workspace needs %zu bytes", need);
-  carve_adjoint<Real>(ctx, (char *)dws, K, ce, pl);
+  carve_adjoint<Real>(ctx, (char *)dws, n, K, ce, pl);
   const State<Real> &st = state<Real>(ctx);
   const Phys &ph = ctx->ph;
   const int N = (int)ctx->N;
@@ -855,10 +860,29 @@ depo_status do_adjoint(depo_ctx *ctx, int n, int ce, const double *hw, double *h
   const double scale = (wmax > 0.0 && mmax > 0.0) ? 1.0 / (wmax * mmax) : 1.0;
   HIP_TRY(hipMemcpyAsync(pl.ad.weights, hw, ctx->S * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
-  // forward run with checkpoints every ce steps
+  // the raw Coulomb sums of a step to and from its Coulomb-tape entry
+  const size_t nb = (size_t)N * sizeof(Real);
+  auto sums_to_tape = [&](int k) -> hipError_t {
+    Real *t = pl.ctape + (size_t)k * 3 * N;
+    hipError_t e = hipMemcpyAsync(t, st.cx, nb, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(t + N, st.cy, nb, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(t + 2 * (size_t)N, st.cz, nb, hipMemcpyDeviceToDevice, s);
+    return e;
+  };
+  auto sums_from_tape = [&](int k) -> hipError_t {
+    const Real *t = pl.ctape + (size_t)k * 3 * N;
+    hipError_t e = hipMemcpyAsync(st.cx, t, nb, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(st.cy, t + N, nb, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(st.cz, t + 2 * (size_t)N, nb, hipMemcpyDeviceToDevice, s);
+    return e;
+  };
+  // forward run with checkpoints every ce steps; the pair sums of every step that does not end
+  // at a checkpoint (or at the final state) are kept, so that the per-segment recomputation
+  // below runs only the O(N) kernels
   for (int k = 0; k < n; ++k) {
     if (k % ce == 0) launch_tape_store<Real>(st, pl.ckpt[k / ce], N, false, s);
     enqueue_step<Real>(ctx, s);
+    if (coul && k % ce != ce - 1 && k != n - 1) HIP_TRY(sums_to_tape((k / ce) * (ce - 1) + k % ce));
   }
   launch_tape_store<Real>(st, pl.fin, N, true, s);
   launch_adj_init<Real>(st, ph, pl.ad, pl.ad.weights, scale, s);
@@ -876,7 +900,12 @@ depo_status do_adjoint(depo_ctx *ctx, int n, int ce, const double *hw, double *h
     if (len > 1) {
       launch_tape_load<Real>(st, pl.ckpt[seg], N, false, s);
       for (int k = 0; k < len - 1; ++k) {
-        enqueue_step<Real>(ctx, s);
+        // the step with its pair sums read from the Coulomb tape (bitwise what the pair kernel gave)
+        launch_prepare<Real>(st, ph, prepare_mode(ctx) | P_KICK_DRIFT, s);
+        if (sr) launch_cells<Real>(st, ph, ctx->n_cells, (ctx->n_cells + 1023) / 1024, s);
+        if (coul) HIP_TRY(sums_from_tape(seg * (ce - 1) + k));
+        if (sr) launch_short_range<Real>(st, ph, ctx->n_cells, s);
+        launch_finish<Real>(st, ph, F_KICK, s);
         launch_tape_store<Real>(st, pl.tape[k], N, false, s);
       }
     }
@@ -1216,10 +1245,10 @@ depo_status depo_adjoint_workspace_bytes(const depo_ctx *ctx, int32_t n_steps, i
   const int K = (n_steps + ckpt_every - 1) / ckpt_every;
   if (ctx->fp64()) {
     AdjPlan<double> pl;
-    *bytes = carve_adjoint<double>(ctx, nullptr, K, ckpt_every, pl);
+    *bytes = carve_adjoint<double>(ctx, nullptr, n_steps, K, ckpt_every, pl);
   } else {
     AdjPlan<float> pl;
-    *bytes = carve_adjoint<float>(ctx, nullptr, K, ckpt_every, pl);
+    *bytes = carve_adjoint<float>(ctx, nullptr, n_steps, K, ckpt_every, pl);
   }
   return DEPO_OK;
 }
