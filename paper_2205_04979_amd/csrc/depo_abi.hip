@@ -102,6 +102,8 @@ struct depo_ctx {
   // captured step graph
   hipGraphExec_t gexec = nullptr;
   hipStream_t cap_stream = nullptr;
+  hipStream_t cap_side = nullptr;               // the graph's short-range branch
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool use_graph = true;
 
   bool fp64() const { return p.real_bytes == 8; }
@@ -376,15 +378,46 @@ template <class Real> void enqueue_step(depo_ctx *ctx, hipStream_t s) {
   launch_finish<Real>(st, ctx->ph, F_KICK, s);
 }
 
+// One step as a graph with two branches after prepare: the direct Coulomb sums, and the cell
+// build + short-range forces (which touch disjoint buffers), joined before finish, so that the
+// O(N) branch fills the pair kernel's tail.
+template <class Real> hipError_t capture_forked_step(depo_ctx *ctx) {
+  const State<Real> &st = state<Real>(ctx);
+  hipStream_t a = ctx->cap_stream, b = ctx->cap_side;
+  launch_prepare<Real>(st, ctx->ph, prepare_mode(ctx) | P_KICK_DRIFT, a);
+  hipError_t e = hipEventRecord(ctx->ev_fork, a);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b, ctx->ev_fork, 0);
+  if (e != hipSuccess) return e;
+  launch_cells<Real>(st, ctx->ph, ctx->n_cells, (ctx->n_cells + 1023) / 1024, b);
+  launch_short_range<Real>(st, ctx->ph, ctx->n_cells, b);
+  if ((e = hipEventRecord(ctx->ev_join, b)) != hipSuccess) return e;
+  enqueue_coulomb<Real>(ctx, a);
+  if ((e = hipStreamWaitEvent(a, ctx->ev_join, 0)) != hipSuccess) return e;
+  launch_finish<Real>(st, ctx->ph, F_KICK, a);
+  return hipGetLastError();
+}
+
 template <class Real> depo_status run_steps(depo_ctx *ctx, int n, hipStream_t s) {
   if (n == 0) return DEPO_OK;
   if (ctx->use_graph) {
     if (!ctx->gexec) {
       if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+      // the P3M pipeline has cell passes of its own: it stays on one branch
+      const bool fork = short_range_on(ctx) && (ctx->p.flags & DEPO_COULOMB) && !ctx->p3m_use;
+      if (fork && !ctx->cap_side) {
+        HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_side, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+      }
       hipGraph_t g = nullptr;
       HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
-      enqueue_step<Real>(ctx, ctx->cap_stream);
-      hipError_t e = hipGetLastError();
+      hipError_t e = hipSuccess;
+      if (fork)
+        e = capture_forked_step<Real>(ctx);
+      else {
+        enqueue_step<Real>(ctx, ctx->cap_stream);
+        e = hipGetLastError();
+      }
       hipError_t e2 = hipStreamEndCapture(ctx->cap_stream, &g);
       if (e != hipSuccess || e2 != hipSuccess) {
         if (g) hipGraphDestroy(g);
@@ -995,6 +1028,9 @@ void depo_destroy(depo_ctx *ctx) {
   if (!ctx) return;
   ctx->drop_graph();
   if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+  if (ctx->cap_side) hipStreamDestroy(ctx->cap_side);
+  if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
   delete ctx;
 }
 
