@@ -267,3 +267,54 @@ def test_fp64_adjoint_per_force_family(name):
             continue
         assert np.allclose(fds[0], fds[1], rtol=2e-4, atol=0)
         assert np.allclose(g[:, c], fds[0], rtol=1e-3, atol=0), (name, c, g[:, c], fds[0])
+
+
+def test_adjoint_64x16k_full_size():
+    """The adjoint workload the benchmark times, at full size (64 samples x 16,384 particles, 100 steps,
+    checkpoints every 10).  FP32 with the symmetric pair adjoint (the benchmark's configuration): its own
+    forward run gives bitwise the J of a plain forward run, and its gradient agrees with the one-sided FP32
+    pair adjoint and with the FP64 adjoint.  FP64: the adjoint agrees with central differences of the
+    library's FP64 forward run, for all samples at once (a sample's J depends only on its own parameters).
+    Tolerances are relative to the largest entry of each gradient column."""
+    from paper_2205_04979_amd.depo import PAIR_KAHAN, PAIR_SYMMETRIC
+    w = make_workload("adjoint-64x16k")
+    f = w.field()
+    n, ce = w.steps, w.extra["ckpt_every"]
+    sp = w.sample_params
+    say("case: adjoint-64x16k full size, S =", w.n_samples, "N =", w.n_particles, "steps", n, "ckpt", ce)
+
+    def J(sim, spp):
+        sim.seed(spp, w.x, w.d, w.qbase)
+        sim.step(n)
+        return np.array([t["j_soft"] for t in sim.tally()])
+
+    g = {}
+    for key in ("sym", "one", "fp64"):
+        sim = gpu_sim(w.params, f, w.offsets, 8 if key == "fp64" else 4)
+        if key == "sym":
+            sim.set_kernel_config(4, 1, 64, mode=PAIR_SYMMETRIC)
+        elif key == "one":
+            sim.set_kernel_config(1, 8, 32, mode=PAIR_KAHAN)
+        j_fwd = J(sim, sp) if key != "one" else None
+        sim.seed(sp, w.x, w.d, w.qbase)
+        g[key] = sim.adjoint(n, ce)
+        if j_fwd is not None:
+            assert np.array_equal(j_fwd, np.array([t["j_soft"] for t in sim.tally()])), key
+        say(key, "gradient of sample 0", g[key][0].tolist())
+        if key == "fp64":
+            fd = np.zeros((w.n_samples, 2))
+            for c in range(2):
+                hp, hm = sp.copy(), sp.copy()
+                hp[:, c] *= 1 + H_REL
+                hm[:, c] *= 1 - H_REL
+                fd[:, c] = (J(sim, hp) - J(sim, hm)) / (2 * H_REL * sp[:, c])
+        del sim
+    for c in range(2):
+        scale = np.abs(g["fp64"][:, c]).max()
+        assert scale > 0
+        dev = {k: np.abs(v[:, c] - g["fp64"][:, c]).max() / scale for k, v in g.items() if k != "fp64"}
+        dev["fd"] = np.abs(fd[:, c] - g["fp64"][:, c]).max() / scale
+        dev["sym-one"] = np.abs(g["sym"][:, c] - g["one"][:, c]).max() / scale
+        say("column", c, "deviation / max |grad|", dev)
+        assert dev["fd"] < 1e-3 and dev["sym"] < 2e-3 and dev["one"] < 2e-3 and dev["sym-one"] < 5e-4, (c, dev)
+    assert np.all(g["sym"][:, 2] == 0) and np.all(g["fp64"][:, 2] == 0)

@@ -365,14 +365,18 @@ def test_fp32_bitwise_deterministic_and_checkpoint_roundtrip(cfg):
         sim.state_upload(blob[:-8])
 
 
-def test_graph_replay_equals_direct_launch():
+@pytest.mark.parametrize("cfg", [(1, 8, 32), (4, 2, 64, 2)])
+def test_graph_replay_equals_direct_launch(cfg):
+    """The captured step (forked into the pair-sum branch and the cell + short-range branch) gives
+    bitwise the state of the same kernels launched one after another, for the one-sided and the
+    symmetric (integer-combined) pair kernels."""
     w = make_workload("single-65k", n=4096, field_n=32)
     f = w.field()
-    say("case: graph replay vs direct launches fp32")
+    say("case: graph replay vs direct launches fp32", cfg)
     out = []
     for graph in (True, False):
         sim, _ = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4, oracle=False)
-        sim.set_kernel_config(1, 8, 32, use_graph=graph)
+        sim.set_kernel_config(*cfg, use_graph=graph)
         for _ in range(3):
             sim.step(4)
             out_k = sim.read()   # eager synchronisation between replays
@@ -452,6 +456,37 @@ def test_fp32_batched_samples_sampled_forces(cfg):
         e = force_error(g["a"][ok], ora.accelerations(ok), coulomb_scale(ora, ok))
         say("steps", steps, "force error max", e.max())
         assert e.max() < 1e-5
+    t = sim.tally()
+    assert len(t) == w.n_samples and all(x["n_alive"] + x["n_dep"] == w.offsets[s + 1] - w.offsets[s]
+                                         for s, x in enumerate(t))
+
+
+@pytest.mark.parametrize("cfg", [(4, 2, 64, 2), (4, 4, 64, 2)])
+def test_fp32_batched_256_full_size_sampled_forces(cfg):
+    """The full 256-sample workload the benchmark times (about 4.45 M particles, sample sizes uniform on
+    2,048..32,768) with the two symmetric shapes its autotuner chooses between: force error of two sampled
+    targets in each of 64 samples against the oracle over the target's own sample, at seed and after 10
+    steps, and per-sample particle conservation in the tally."""
+    w = make_workload("batched-256")
+    f = w.field()
+    say("case: batched-256 full size fp32, S =", w.n_samples, "N =", w.n_particles, cfg)
+    sim, _ = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4, oracle=False)
+    sim.set_kernel_config(*cfg)
+    sim.eval_accel()
+    rng = np.random.default_rng(2)
+    samples = np.sort(rng.choice(w.n_samples, 64, replace=False))
+    targets = np.sort(np.concatenate([rng.choice(np.arange(w.offsets[s], w.offsets[s + 1]), 2, replace=False)
+                                      for s in samples]))
+    for steps in (0, 10):
+        if steps:
+            sim.step(steps)
+            sim.eval_accel()
+        g = sim.read()
+        ora = oracle_from_snapshot(w.params, f, g, w.d, w.qbase, w.offsets, w.sample_params, g["dep_step"])
+        ok = targets[g["dep_step"][targets] == 0]
+        e = force_error(g["a"][ok], ora.accelerations(ok), coulomb_scale(ora, ok))
+        say("steps", steps, "targets", ok.size, "force error max", e.max(), "median", np.median(e))
+        assert ok.size >= 120 and e.max() < 1e-5
     t = sim.tally()
     assert len(t) == w.n_samples and all(x["n_alive"] + x["n_dep"] == w.offsets[s + 1] - w.offsets[s]
                                          for s, x in enumerate(t))
