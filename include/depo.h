@@ -229,9 +229,11 @@ depo_status depo_set_kernel_config(depo_ctx *ctx, int32_t targets_per_lane, int3
  * alpha = alpha_h / h (h the larger spacing, 0 < alpha_h <= 2) and short-range
  * cutoff r_max = rmax_alpha / alpha (2 <= rmax_alpha <= 6).  Triangular-
  * shaped-cloud assignment and interpolation, image-summed Green's function
- * deconvolved by the squared TSC transfer, FP64 mesh and FFTs, deterministic.
- * Must be called before depo_set_layout (it sizes the workspace: about
- * 80 B per mesh node); needs a single-sample layout with L >= 3 r_max, and
+ * deconvolved by the squared TSC transfer (built in FP64), mesh and FFTs in
+ * the form's precision (complex FP32 in the FP32 form, FP64 in the FP64
+ * form), deterministic.  Must be called before depo_set_layout (it sizes the
+ * workspace: about 40 B per mesh node in the FP32 form, 80 B in the FP64
+ * form); needs a single-sample layout with L >= 3 r_max, and
  * selects P3M as the Coulomb solver (depo_set_kernel_config switches between
  * it, mode DEPO_PAIR_P3M, and the direct modes).  The adjoint rejects P3M.
  * DEPO_E_STATE after the layout is set, DEPO_E_INVALID for bad sizes. */

@@ -172,9 +172,10 @@ size_t carve(depo_ctx *ctx, char *base, State<Real> &st) {
   if (ctx->p3m_cfg) {
     P3mDev &m = ctx->pm;
     const size_t total = (size_t)m.nx * m.P * m.P, ncell = (size_t)m.ncx * m.ncy * m.ncy;
-    for (int c = 0; c < 3; ++c) m.ghat[c] = (double2 *)take(total * sizeof(double2));
-    m.rho = (double2 *)take(total * sizeof(double2));
-    m.work = (double2 *)take(total * sizeof(double2));
+    const size_t me = sizeof(Real) == 4 ? sizeof(float2) : sizeof(double2);   // mesh element
+    for (int c = 0; c < 3; ++c) m.ghat[c] = take(total * me);
+    m.rho = take(2 * total * me);   // rho, then work
+    m.work = m.rho ? (void *)((char *)m.rho + total * me) : nullptr;
     m.qmesh = (unsigned long long *)take((size_t)m.nx * m.nc * m.nc * 8);
     m.slong = (double *)take(3 * N * sizeof(double));
     m.cell_of = (int32_t *)take(N * 4);
@@ -624,7 +625,7 @@ depo_status do_seed(depo_ctx *ctx, const depo_sample_params *sp, const double *h
     launch_clear_int((int32_t *)m.qmesh, 2 * (size_t)m.nx * m.nc * m.nc, s);
     launch_clear_int(m.counts, (size_t)m.ncx * m.ncy * m.ncy, s);
     if (!ctx->p3m_green) {
-      p3m_setup_green(m, ctx->p.L, kP3mImages, s);
+      p3m_setup_green(m, ctx->p.L, kP3mImages, sizeof(Real) == 4, s);
       ctx->p3m_green = true;
     }
     HIP_TRY(hipGetLastError());

@@ -12,11 +12,13 @@
 // the direct sum) minus the erf field, over nearest-image pairs closer than
 // r_max, found through a cell list with cells of at least r_max.
 //
-// Everything on the mesh is FP64: charge assignment adds 64-bit fixed-point
-// weights with integer atomics (order independent), the FFTs are radix-2
-// Cooley-Tukey passes over mesh lines staged in LDS, and the short-range sum is
-// a gather over cell-sorted neighbours in a fixed order, so results are
-// bitwise reproducible.
+// Charge assignment adds 64-bit fixed-point weights with integer atomics (order
+// independent), the FFTs are radix-2 Cooley-Tukey passes over mesh lines staged
+// in LDS, and the short-range sum is a gather over cell-sorted neighbours in a
+// fixed order, so results are bitwise reproducible.  The mesh holds complex
+// values in the form's precision (FP32 form: float2, half the bytes of every
+// mesh pass; FP64 form: double2); the Green's function is always built and
+// transformed in FP64 and only then rounded to the mesh type.
 #include <type_traits>
 
 #include "common.hpp"
@@ -31,6 +33,21 @@ constexpr int kFftLds = 2048;   // complex values per FFT workgroup (32 KB of LD
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <class T> __device__ __forceinline__ T cplx(double re, double im);
+template <> __device__ __forceinline__ double2 cplx<double2>(double re, double im) { return make_double2(re, im); }
+template <> __device__ __forceinline__ float2 cplx<float2>(double re, double im) {
+  return make_float2((float)re, (float)im);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// mesh element of a form
+template <class Real> using MeshT = typename std::conditional<sizeof(Real) == 4, float2, double2>::type;
 
 // Continuous mesh coordinates of particle i (x periodic in [0, nx); y, z in [1, nc - 2]).
 template <class Real>
@@ -55,9 +72,10 @@ __device__ __forceinline__ void tsc(double g, int &i, double (&w)[3]) {
   w[2] = 0.5 * (0.5 + dl) * (0.5 + dl);
 }
 
-// Erf field of a unit charge at displacement (dx, dy, dz), summed over the x images n = -M..M.
-__global__ void k_p3m_green(P3mDev m, double L, int images, double2 *__restrict__ gx_, double2 *__restrict__ gy_,
-                            double2 *__restrict__ gz_) {
+// Erf field of a unit charge at displacement (dx, dy, dz), summed over the x images n = -M..M:
+// all three components (comp < 0) or component comp alone into gx_.
+__global__ void k_p3m_green(P3mDev m, double L, int images, int comp, double2 *__restrict__ gx_,
+                            double2 *__restrict__ gy_, double2 *__restrict__ gz_) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)m.nx * m.P * m.P;
   if (e >= total) return;
@@ -79,27 +97,44 @@ __global__ void k_p3m_green(P3mDev m, double L, int images, double2 *__restrict_
     ey += f * dy;
     ez += f * dz;
   }
-  gx_[e] = make_double2(ex, 0.0);
-  gy_[e] = make_double2(ey, 0.0);
-  gz_[e] = make_double2(ez, 0.0);
+  if (comp < 0) {
+    gx_[e] = make_double2(ex, 0.0);
+    gy_[e] = make_double2(ey, 0.0);
+    gz_[e] = make_double2(ez, 0.0);
+  } else {
+    gx_[e] = make_double2(comp == 0 ? ex : (comp == 1 ? ey : ez), 0.0);
+  }
 }
 
 // Divide the transformed Green's functions by the squared TSC transfer sinc^3 per axis.
 __device__ __forceinline__ double sinc_pi(double u) { return u == 0.0 ? 1.0 : sin(M_PI * u) / (M_PI * u); }
+
+__device__ __forceinline__ double tsc_inv_transfer2(const P3mDev &m, int64_t e) {
+  const int iz = (int)(e % m.P), iy = (int)((e / m.P) % m.P), ix = (int)(e / ((int64_t)m.P * m.P));
+  auto freq = [](int i, int n) { return (double)(i < (n + 1) / 2 ? i : i - n) / n; };   // cycles per node
+  const double sx = sinc_pi(freq(ix, m.nx)), sy = sinc_pi(freq(iy, m.P)), sz = sinc_pi(freq(iz, m.P));
+  const double W = sx * sx * sx * sy * sy * sy * sz * sz * sz;
+  return 1.0 / (W * W);
+}
 
 __global__ void k_p3m_deconv(P3mDev m, double2 *__restrict__ gx_, double2 *__restrict__ gy_,
                              double2 *__restrict__ gz_) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)m.nx * m.P * m.P;
   if (e >= total) return;
-  const int iz = (int)(e % m.P), iy = (int)((e / m.P) % m.P), ix = (int)(e / ((int64_t)m.P * m.P));
-  auto freq = [](int i, int n) { return (double)(i < (n + 1) / 2 ? i : i - n) / n; };   // cycles per node
-  const double sx = sinc_pi(freq(ix, m.nx)), sy = sinc_pi(freq(iy, m.P)), sz = sinc_pi(freq(iz, m.P));
-  const double W = sx * sx * sx * sy * sy * sy * sz * sz * sz;
-  const double inv = 1.0 / (W * W);
+  const double inv = tsc_inv_transfer2(m, e);
   gx_[e] = make_double2(gx_[e].x * inv, gx_[e].y * inv);
   gy_[e] = make_double2(gy_[e].x * inv, gy_[e].y * inv);
   gz_[e] = make_double2(gz_[e].x * inv, gz_[e].y * inv);
+}
+
+// One transformed FP64 component, deconvolved and rounded to an FP32 mesh array.
+__global__ void k_p3m_deconv_f32(P3mDev m, const double2 *__restrict__ g, float2 *__restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)m.nx * m.P * m.P;
+  if (e >= total) return;
+  const double inv = tsc_inv_transfer2(m, e);
+  out[e] = make_float2((float)(g[e].x * inv), (float)(g[e].y * inv));
 }
 
 // Complex FFT of length n = 2^log2n along lines of the mesh: line l starts at
@@ -109,11 +144,12 @@ __global__ void k_p3m_deconv(P3mDev m, double2 *__restrict__ gx_, double2 *__res
 // a power of two, so all index arithmetic is shifts and masks.
 constexpr int kFftLog2Lds = 11;
 static_assert((1 << kFftLog2Lds) == kFftLds, "kFftLds is 2^kFftLog2Lds");
-__global__ __launch_bounds__(256) void k_fft_lines(double2 *__restrict__ data, int log2n, int log2inner,
+template <class T>
+__global__ __launch_bounds__(256) void k_fft_lines(T *__restrict__ data, int log2n, int log2inner,
                                                    int64_t inner_stride, int64_t outer_stride, int64_t point_stride,
                                                    int sign, int points_contiguous) {
-  __shared__ double2 buf[kFftLds];
-  __shared__ double2 tw[kFftLds / 2];
+  __shared__ T buf[kFftLds];
+  __shared__ T tw[kFftLds / 2];
   const int n = 1 << log2n;
   const int log2lpw = kFftLog2Lds - log2n;   // lines per workgroup: 2^log2lpw
   const int64_t l0 = (int64_t)blockIdx.x << log2lpw;
@@ -121,7 +157,7 @@ __global__ __launch_bounds__(256) void k_fft_lines(double2 *__restrict__ data, i
   for (int k = threadIdx.x; k < n / 2; k += blockDim.x) {
     double s, c;
     sincospi(2.0 * k / n, &s, &c);
-    tw[k] = make_double2(c, sign * s);
+    tw[k] = cplx<T>(c, sign * s);   // in FP64, then rounded to the mesh type
   }
   auto addr = [&](int line, int p) {
     const int64_t l = l0 + line;
@@ -145,19 +181,19 @@ __global__ __launch_bounds__(256) void k_fft_lines(double2 *__restrict__ data, i
       const int line = b >> (log2n - 2), k = b & ((n >> 2) - 1);
       const int pos = k & (half - 1);
       const int i0 = (line << log2n) + ((k >> (lg - 1)) << (lg + 1)) + pos;
-      const double2 w1 = tw[pos << (log2n - lg)];
-      const double2 w2a = tw[pos << (log2n - lg - 1)], w2b = tw[(pos + half) << (log2n - lg - 1)];
-      const double2 a0 = buf[i0], a1 = buf[i0 + half], a2 = buf[i0 + 2 * half], a3 = buf[i0 + 3 * half];
-      double2 v = cmul(w1, a1);
-      const double2 b0 = make_double2(a0.x + v.x, a0.y + v.y), b1 = make_double2(a0.x - v.x, a0.y - v.y);
+      const T w1 = tw[pos << (log2n - lg)];
+      const T w2a = tw[pos << (log2n - lg - 1)], w2b = tw[(pos + half) << (log2n - lg - 1)];
+      const T a0 = buf[i0], a1 = buf[i0 + half], a2 = buf[i0 + 2 * half], a3 = buf[i0 + 3 * half];
+      T v = cmul(w1, a1);
+      const T b0 = cadd(a0, v), b1 = csub(a0, v);
       v = cmul(w1, a3);
-      const double2 b2 = make_double2(a2.x + v.x, a2.y + v.y), b3 = make_double2(a2.x - v.x, a2.y - v.y);
+      const T b2 = cadd(a2, v), b3 = csub(a2, v);
       v = cmul(w2a, b2);
-      buf[i0] = make_double2(b0.x + v.x, b0.y + v.y);
-      buf[i0 + 2 * half] = make_double2(b0.x - v.x, b0.y - v.y);
+      buf[i0] = cadd(b0, v);
+      buf[i0 + 2 * half] = csub(b0, v);
       v = cmul(w2b, b3);
-      buf[i0 + half] = make_double2(b1.x + v.x, b1.y + v.y);
-      buf[i0 + 3 * half] = make_double2(b1.x - v.x, b1.y - v.y);
+      buf[i0 + half] = cadd(b1, v);
+      buf[i0 + 3 * half] = csub(b1, v);
     }
     __syncthreads();
   }
@@ -167,10 +203,10 @@ __global__ __launch_bounds__(256) void k_fft_lines(double2 *__restrict__ data, i
       const int line = b >> (log2n - 1), k = b & ((n >> 1) - 1);
       const int pos = k & (half - 1);
       const int i = (line << log2n) + ((k >> (lg - 1)) << lg) + pos;
-      const double2 u = buf[i];
-      const double2 v = cmul(tw[pos << (log2n - lg)], buf[i + half]);
-      buf[i] = make_double2(u.x + v.x, u.y + v.y);
-      buf[i + half] = make_double2(u.x - v.x, u.y - v.y);
+      const T u = buf[i];
+      const T v = cmul(tw[pos << (log2n - lg)], buf[i + half]);
+      buf[i] = cadd(u, v);
+      buf[i + half] = csub(u, v);
     }
     __syncthreads();
   }
@@ -284,7 +320,8 @@ __global__ __launch_bounds__(256) void k_p3m_assign(State<Real> st, Phys ph, P3m
 }
 
 // Fixed-point charges into the zero-padded complex mesh (every node written); the charge mesh is cleared.
-__global__ void k_p3m_load(P3mDev m, unsigned long long *__restrict__ qmesh, double2 *__restrict__ rho) {
+template <class T>
+__global__ void k_p3m_load(P3mDev m, unsigned long long *__restrict__ qmesh, T *__restrict__ rho) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)m.nx * m.P * m.P;
   if (e >= total) return;
@@ -295,11 +332,11 @@ __global__ void k_p3m_load(P3mDev m, unsigned long long *__restrict__ qmesh, dou
     v = (double)(long long)qmesh[o] / *m.q_scale;
     qmesh[o] = 0ull;
   }
-  rho[e] = make_double2(v, 0.0);
+  rho[e] = cplx<T>(v, 0.0);
 }
 
-__global__ void k_p3m_mul(P3mDev m, const double2 *__restrict__ a, const double2 *__restrict__ g,
-                          double2 *__restrict__ out) {
+template <class T>
+__global__ void k_p3m_mul(P3mDev m, const T *__restrict__ a, const T *__restrict__ g, T *__restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)m.nx * m.P * m.P) return;
   out[e] = cmul(a[e], g[e]);
@@ -308,19 +345,20 @@ __global__ void k_p3m_mul(P3mDev m, const double2 *__restrict__ a, const double2
 // Two real fields in one transform: out = a g1 + i a g2.  The charge and both Green's functions
 // are real on the mesh, so the inverse transform of a g1 and of a g2 are real, and the inverse
 // transform of out is E1 + i E2.
-__global__ void k_p3m_mul2(P3mDev m, const double2 *__restrict__ a, const double2 *__restrict__ g1,
-                           const double2 *__restrict__ g2, double2 *__restrict__ out) {
+template <class T>
+__global__ void k_p3m_mul2(P3mDev m, const T *__restrict__ a, const T *__restrict__ g1, const T *__restrict__ g2,
+                           T *__restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)m.nx * m.P * m.P) return;
-  const double2 p = cmul(a[e], g1[e]), q = cmul(a[e], g2[e]);
-  out[e] = make_double2(p.x - q.y, p.y + q.x);
+  const T p = cmul(a[e], g1[e]), q = cmul(a[e], g2[e]);
+  out[e] = T{p.x - q.y, p.y + q.x};
 }
 
 // TSC interpolation of the unnormalised inverse transform: its real part to out_re and, when
 // out_im is given, its imaginary part (a second real field) to out_im.
 template <class Real>
 __global__ void k_p3m_interp(State<Real> st, Phys ph, P3mDev m, const int32_t *__restrict__ order,
-                             const double2 *__restrict__ E, double *__restrict__ out_re,
+                             const MeshT<Real> *__restrict__ E, double *__restrict__ out_re,
                              double *__restrict__ out_im) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;   // cell order, for locality of the mesh reads
   if (k >= ph.N) return;
@@ -340,9 +378,9 @@ __global__ void k_p3m_interp(State<Real> st, Phys ph, P3mDev m, const int32_t *_
     for (int b = 0; b < 3; ++b)
       for (int c = 0; c < 3; ++c) {
         const double w = wx[a] * wy[b] * wz[c];
-        const double2 v = E[((int64_t)jx * m.P + (iy + b - 1)) * m.P + (iz + c - 1)];
-        s += w * v.x;
-        t += w * v.y;
+        const MeshT<Real> v = E[((int64_t)jx * m.P + (iy + b - 1)) * m.P + (iz + c - 1)];
+        s += w * (double)v.x;
+        t += w * (double)v.y;
       }
   }
   const double norm = 1.0 / ((double)m.nx * m.P * m.P);
@@ -637,29 +675,40 @@ int ilog2(int n) {
 }
 
 // 3D transform of the padded mesh: lines along z, y, x.
-void fft3d(const P3mDev &m, double2 *d, int sign, hipStream_t s) {
+template <class T> void fft3d(const P3mDev &m, T *d, int sign, hipStream_t s) {
   const int64_t P = m.P, nx = m.nx;
   const int64_t total = nx * P * P;
   const int lp = ilog2((int)P);
   // z: points contiguous, line l at l * P
-  hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)(total / kFftLds)), dim3(256), 0, s, d, lp, 0, (int64_t)0, P,
+  hipLaunchKernelGGL(k_fft_lines<T>, dim3((unsigned)(total / kFftLds)), dim3(256), 0, s, d, lp, 0, (int64_t)0, P,
                      (int64_t)1, sign, 1);
   // y: line (ix, iz) at ix P^2 + iz, points P apart
-  hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)(total / kFftLds)), dim3(256), 0, s, d, lp, lp, (int64_t)1, P * P,
+  hipLaunchKernelGGL(k_fft_lines<T>, dim3((unsigned)(total / kFftLds)), dim3(256), 0, s, d, lp, lp, (int64_t)1, P * P,
                      P, sign, 0);
   // x: line (iy, iz) at iy P + iz, points P^2 apart
-  hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)(total / kFftLds)), dim3(256), 0, s, d, ilog2((int)nx), 0,
+  hipLaunchKernelGGL(k_fft_lines<T>, dim3((unsigned)(total / kFftLds)), dim3(256), 0, s, d, ilog2((int)nx), 0,
                      (int64_t)0, (int64_t)1, P * P, sign, 0);
 }
 
 }  // namespace
 
-void p3m_setup_green(const P3mDev &m, double L, int images, hipStream_t s) {
+void p3m_setup_green(const P3mDev &m, double L, int images, bool fp32_mesh, hipStream_t s) {
   const int64_t total = (int64_t)m.nx * m.P * m.P;
   const unsigned g = (unsigned)((total + 255) / 256);
-  hipLaunchKernelGGL(k_p3m_green, dim3(g), dim3(256), 0, s, m, L, images, m.ghat[0], m.ghat[1], m.ghat[2]);
-  for (int c = 0; c < 3; ++c) fft3d(m, m.ghat[c], -1, s);
-  hipLaunchKernelGGL(k_p3m_deconv, dim3(g), dim3(256), 0, s, m, m.ghat[0], m.ghat[1], m.ghat[2]);
+  if (fp32_mesh) {
+    // each component in FP64 in the rho + work region (one double2 mesh), then rounded
+    double2 *tmp = (double2 *)m.rho;
+    for (int c = 0; c < 3; ++c) {
+      hipLaunchKernelGGL(k_p3m_green, dim3(g), dim3(256), 0, s, m, L, images, c, tmp, tmp, tmp);
+      fft3d<double2>(m, tmp, -1, s);
+      hipLaunchKernelGGL(k_p3m_deconv_f32, dim3(g), dim3(256), 0, s, m, tmp, (float2 *)m.ghat[c]);
+    }
+  } else {
+    double2 *gh[3] = {(double2 *)m.ghat[0], (double2 *)m.ghat[1], (double2 *)m.ghat[2]};
+    hipLaunchKernelGGL(k_p3m_green, dim3(g), dim3(256), 0, s, m, L, images, -1, gh[0], gh[1], gh[2]);
+    for (int c = 0; c < 3; ++c) fft3d<double2>(m, gh[c], -1, s);
+    hipLaunchKernelGGL(k_p3m_deconv, dim3(g), dim3(256), 0, s, m, gh[0], gh[1], gh[2]);
+  }
   hipLaunchKernelGGL(k_p3m_table, dim3((kSrTable + 256) / 256), dim3(256), 0, s, m, m.table);
 }
 
@@ -675,16 +724,19 @@ template <class Real> void launch_p3m(const State<Real> &st, const Phys &ph, con
   hipLaunchKernelGGL(k_p3m_sort, dim3((unsigned)ncell), dim3(256), 0, s, ncell, m.starts, m.sorted, m.counts);
   hipLaunchKernelGGL((k_p3m_assign<Real>), dim3((unsigned)ncell), dim3(256), 0, s, st, ph, m, m.starts, m.sorted,
                      m.qmesh);
-  hipLaunchKernelGGL(k_p3m_load, dim3(gm), dim3(256), 0, s, m, m.qmesh, m.rho);
-  fft3d(m, m.rho, -1, s);
+  using T = MeshT<Real>;
+  T *rho = (T *)m.rho, *work = (T *)m.work;
+  const T *g0 = (const T *)m.ghat[0], *g1 = (const T *)m.ghat[1], *g2 = (const T *)m.ghat[2];
+  hipLaunchKernelGGL(k_p3m_load<T>, dim3(gm), dim3(256), 0, s, m, m.qmesh, rho);
+  fft3d<T>(m, rho, -1, s);
   // E_x + i E_y from one inverse transform, then E_z
-  hipLaunchKernelGGL(k_p3m_mul2, dim3(gm), dim3(256), 0, s, m, m.rho, m.ghat[0], m.ghat[1], m.work);
-  fft3d(m, m.work, +1, s);
-  hipLaunchKernelGGL((k_p3m_interp<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.sorted, m.work, m.slong,
+  hipLaunchKernelGGL(k_p3m_mul2<T>, dim3(gm), dim3(256), 0, s, m, rho, g0, g1, work);
+  fft3d<T>(m, work, +1, s);
+  hipLaunchKernelGGL((k_p3m_interp<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.sorted, work, m.slong,
                      m.slong + ph.N);
-  hipLaunchKernelGGL(k_p3m_mul, dim3(gm), dim3(256), 0, s, m, m.rho, m.ghat[2], m.work);
-  fft3d(m, m.work, +1, s);
-  hipLaunchKernelGGL((k_p3m_interp<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.sorted, m.work,
+  hipLaunchKernelGGL(k_p3m_mul<T>, dim3(gm), dim3(256), 0, s, m, rho, g2, work);
+  fft3d<T>(m, work, +1, s);
+  hipLaunchKernelGGL((k_p3m_interp<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.sorted, work,
                      m.slong + 2 * (int64_t)ph.N, (double *)nullptr);
   SrRec<Real> *rec = (SrRec<Real> *)m.rec;
   hipLaunchKernelGGL((k_p3m_records<Real>), dim3(gp), dim3(256), 0, s, st, ph, m.sorted, rec);

@@ -47,15 +47,17 @@ struct P3mDev {
   double hx, hy;          // mesh spacings [m]
   double alpha, rmax;     // splitting parameter [1/m] and short-range cutoff [m]
   const double *q_scale;  // device: fixed-point units per unit of scaled charge
-  double2 *ghat[3];       // transformed, deconvolved Green's function per field component
-  double2 *rho, *work;    // transformed charge; one field component
+  // mesh arrays of nx x P x P complex values: float2 in the FP32 form, double2 in the FP64 form
+  void *ghat[3];          // transformed, deconvolved Green's function per field component
+  void *rho, *work;       // transformed charge; one field component (FP32 form: adjacent, so that
+                          // together they hold one double2 mesh for the Green's function set-up)
   unsigned long long *qmesh;   // fixed-point TSC charge, nx x nc x nc (zero between steps)
   double *slong;          // [3][N] long-range part at the particles [1/m^2]
   int32_t *cell_of, *counts, *starts, *fill, *sorted;   // short-range cell list
   void *rec;              // cell-sorted source records of the short-range pass (N records)
   float2 *table;          // tabulated short-range profile (FP32 form), 4096 intervals + (0, 0)
 };
-void p3m_setup_green(const P3mDev &m, double L, int images, hipStream_t s);
+void p3m_setup_green(const P3mDev &m, double L, int images, bool fp32_mesh, hipStream_t s);
 template <class Real> void launch_p3m(const State<Real> &st, const Phys &ph, const P3mDev &m, hipStream_t s);
 
 // One-dimensional Eulerian low-fidelity model, one lane per particle class.

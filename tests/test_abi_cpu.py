@@ -205,7 +205,14 @@ def test_p3m_configuration_validation(depo):
     assert L.depo_set_kernel_config(ctx._h, 1, 8, 64, 3, 1) == depo.OK
     small = depo.Context(physical_params(), 4)
     small.set_layout([0, 1000], 16, 16, 16)
-    assert ctx.workspace_bytes() > small.workspace_bytes() + 64 * 64 * 64 * 16 * 5        # five complex meshes
+    assert ctx.workspace_bytes() > small.workspace_bytes() + 64 * 64 * 64 * 8 * 5         # five FP32 complex meshes
+    ctx64, small64 = depo.Context(physical_params(), 8), depo.Context(physical_params(), 8)
+    assert L.depo_set_p3m(ctx64._h, 64, 32, 0.5, 3.5) == depo.OK
+    ctx64.set_layout([0, 1000], 16, 16, 16)
+    small64.set_layout([0, 1000], 16, 16, 16)
+    mesh64 = ctx64.workspace_bytes() - small64.workspace_bytes()
+    assert mesh64 > 64 * 64 * 64 * 16 * 5                                                   # five FP64 complex meshes
+    assert ctx.workspace_bytes() - small.workspace_bytes() < mesh64 - 64 * 64 * 64 * 8 * 5 + 1
     coarse = depo.Context(physical_params(), 4)
     assert L.depo_set_p3m(coarse._h, 16, 16, 0.3, 6.0) == depo.OK                        # r_max > L / 3
     with pytest.raises(depo.DepoError):
