@@ -508,7 +508,9 @@ __global__ void k_p3m_records(State<Real> st, Phys ph, const int32_t *__restrict
 
 constexpr int kSrLds = 65536;    // bytes of LDS for staged neighbour records (FP64 form)
 constexpr int kSrLdsF32 = 40960; // the same for the FP32 form, which also holds the profile table
-constexpr int kSrWaves = 8;      // waves per cell: each takes every 8th staged source
+constexpr int kSrWaves = 8;      // waves per cell
+constexpr int kSrLanes = 64 * kSrWaves;
+constexpr int kSrMaxSlices = 32; // at most this many threads share one target
 constexpr int kSrTable = 4096;   // intervals of the tabulated short-range profile (FP32 form)
 
 // Short-range force profile g(s) = erfc(s) + (2 s / sqrt(pi)) exp(-s^2), s = alpha r, so that the
@@ -530,8 +532,10 @@ __global__ void k_p3m_table(P3mDev m, float2 *__restrict__ tab) {
 // Short range (Coulomb with the overlap clamp minus the erf field) over nearest-image neighbours
 // closer than r_max, added to the long-range part; result in units of the x quantum.  One
 // workgroup per cell: the records of the 27 neighbouring cells are staged in LDS (in chunks when
-// they exceed it); the cell's targets take one lane each in every wave, and the waves split the
-// staged sources, combined in LDS in a fixed order.  FP32: branch-free tabulated profile read from
+// they exceed it); the cell's nb targets (up to 512 at a time) share the 512 threads, S =
+// 512 / nb threads per target (at most 32), and thread g takes target g mod nb and every S-th
+// staged source from slice g / nb on; the S partial sums of a target are combined in FP64 in
+// slice order.  FP32: branch-free tabulated profile read from
 // a copy of the table in LDS, in y/z position quanta (overlapping pairs, which are rare, take the
 // exact clamp); FP64: the exact expressions, in metres.
 template <class Real>
@@ -547,7 +551,7 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
   constexpr int CAP = (sizeof(Real) == 4 ? kSrLdsF32 : kSrLds) / sizeof(SrRec<Real>);
   __shared__ SrRec<Real> src[CAP];
   __shared__ float2 stab[sizeof(Real) == 4 ? kSrTable + 1 : 1];
-  __shared__ Real part[kSrWaves][3][64];
+  __shared__ Real part[3][kSrLanes];
   __shared__ int32_t rb[27], rn[27], roff[28];
   const int c = blockIdx.x;
   const int cz = c % m.ncy, cy = (c / m.ncy) % m.ncy, cx = c / (m.ncy * m.ncy);
@@ -555,7 +559,6 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
   if (nt == 0) return;   // uniform: the whole workgroup leaves
   if constexpr (sizeof(Real) == 4)   // read after the barriers below
     for (int k = threadIdx.x; k <= kSrTable; k += 64 * kSrWaves) stab[k] = tab[k];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (threadIdx.x < 27) {
     const int ox = (int)threadIdx.x / 9 - 1, oy = ((int)threadIdx.x / 3) % 3 - 1, oz = (int)threadIdx.x % 3 - 1;
     int x = cx + ox;
@@ -585,10 +588,13 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
   const float tq = (float)(kSrTable * ph.ur / m.rmax);
   const float near2q = (float)(ph.near2 * (ph.ux / ph.ur) * (ph.ux / ph.ur));
   const bool once = total <= CAP;   // all sources fit: staged once for every target block
-  for (int tb = 0; tb < nt; tb += 64) {
-    const int kt = tb + lane;
-    const bool has = kt < nt;
-    const SrRec<Real> me = rec[t0 + (has ? kt : 0)];
+  for (int tb = 0; tb < nt; tb += kSrLanes) {
+    const int nb = min(kSrLanes, nt - tb);
+    const int S = min(kSrLanes / nb, kSrMaxSlices);   // threads per target
+    const int g = threadIdx.x;
+    const bool has = g < nb * S;
+    const int t = has ? g % nb : 0, slice = has ? g / nb : 0;
+    const SrRec<Real> me = rec[t0 + tb + t];
     Real sx = 0, sy = 0, sz = 0;
     for (int cb = 0; cb < total; cb += CAP) {
       const int n = min(CAP, total - cb);
@@ -597,12 +603,13 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
         // staged entries [cb, cb + n) of the concatenated 27 cell ranges, cell by cell
         for (int k = 0; k < 27; ++k) {
           const int lo = max(roff[k], cb), hi = min(roff[k + 1], cb + n);
-          for (int g = lo + (int)threadIdx.x; g < hi; g += 64 * kSrWaves) src[g - cb] = rec[rb[k] + (g - roff[k])];
+          for (int q = lo + (int)threadIdx.x; q < hi; q += kSrLanes) src[q - cb] = rec[rb[k] + (q - roff[k])];
         }
         __syncthreads();
       }
+      if (!has) continue;
 #pragma unroll 4
-      for (int e = w; e < n; e += kSrWaves) {
+      for (int e = slice; e < n; e += S) {
         const SrRec<Real> s = src[e];
         if constexpr (sizeof(Real) == 4) {
           // y/z quanta; r2 floored so that r = 0 (the target itself) gives a finite f times dx = 0
@@ -644,19 +651,18 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
         }
       }
     }
-    part[w][0][lane] = sx;
-    part[w][1][lane] = sy;
-    part[w][2][lane] = sz;
+    part[0][g] = sx;
+    part[1][g] = sy;
+    part[2][g] = sz;
     __syncthreads();
-    if (w == 0 && has) {
+    if (g < nb) {
       double ax = 0.0, ay = 0.0, az = 0.0;
-#pragma unroll
-      for (int q = 0; q < kSrWaves; ++q) {
-        ax += (double)part[q][0][lane];
-        ay += (double)part[q][1][lane];
-        az += (double)part[q][2][lane];
+      for (int q = 0; q < S; ++q) {
+        ax += (double)part[0][q * nb + g];
+        ay += (double)part[1][q * nb + g];
+        az += (double)part[2][q * nb + g];
       }
-      const int i = sorted[t0 + kt];
+      const int i = sorted[t0 + tb + g];
       const double u2 = ph.ux * ph.ux;
       // the FP32 sums are in y/z quanta: (u_x / u_r)^2 takes them to x quanta, like slong * u_x^2
       const double us = sizeof(Real) == 4 ? (ph.ux / ph.ur) * (ph.ux / ph.ur) : u2;
