@@ -587,6 +587,9 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
   const float kx = (float)(ph.ux / ph.ur), aq = (float)(m.alpha * ph.ur), c2q = (float)(2.0 * m.alpha * ph.ur / sqrt(M_PI));
   const float tq = (float)(kSrTable * ph.ur / m.rmax);
   const float near2q = (float)(ph.near2 * (ph.ux / ph.ur) * (ph.ux / ph.ur));
+  // beyond this (r_max squared in quanta, plus 1e-4 for rounding) the table coordinate u is
+  // surely past the last interval, so the pair adds an exact zero
+  const float skip2q = (float)((m.rmax / ph.ur) * (m.rmax / ph.ur) * 1.0001);
   const bool once = total <= CAP;   // all sources fit: staged once for every target block
   for (int tb = 0; tb < nt; tb += kSrLanes) {
     const int nb = min(kSrLanes, nt - tb);
@@ -617,6 +620,7 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
           const float dy = (float)((int32_t)me.y - (int32_t)s.y);
           const float dz = (float)((int32_t)me.z - (int32_t)s.z);
           const float r2 = fmaxf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), 1e-20f);
+          if (!__builtin_amdgcn_ballot_w64(r2 < skip2q)) continue;   // no active lane within r_max
           const float inv = __builtin_amdgcn_rsqf(r2);
           const float r = r2 * inv;
           const float u = fminf(r * tq, (float)kSrTable);   // u >= kSrTable: beyond r_max, entry (0, 0)
