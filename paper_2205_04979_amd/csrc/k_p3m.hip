@@ -403,14 +403,22 @@ __device__ __forceinline__ int3 sr_cell(const State<Real> &st, const Phys &ph, c
   return make_int3(cx, cy, cz);
 }
 
+// Cell id and octant of the particle within it (4 hx + 2 hy + hz, from the cell's halves along
+// each axis), packed as 8 id + octant.
 template <class Real>
 __global__ void k_p3m_bin(State<Real> st, Phys ph, P3mDev m, int32_t *__restrict__ cell_of,
                           int32_t *__restrict__ counts) {
+  using SPos = typename std::make_signed<typename Prec<Real>::Pos>::type;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ph.N) return;
   const int3 c = sr_cell<Real>(st, ph, m, i);
   const int id = (c.x * m.ncy + c.y) * m.ncy + c.z;
-  cell_of[i] = id;
+  const double x = (double)st.px[i] * ph.ux;
+  const double y = (double)(SPos)st.py[i] * ph.ur;
+  const double z = (double)(SPos)st.pz[i] * ph.ur;
+  const int hx = (x / ph.L * m.ncx - c.x) >= 0.5, hy = ((y + ph.R) / (2.0 * ph.R) * m.ncy - c.y) >= 0.5,
+            hz = ((z + ph.R) / (2.0 * ph.R) * m.ncy - c.z) >= 0.5;
+  cell_of[i] = 8 * id + 4 * hx + 2 * hy + hz;
   atomicAdd(counts + id, 1);
 }
 
@@ -444,27 +452,31 @@ __global__ void k_p3m_scatter(int32_t N, const int32_t *__restrict__ cell_of, in
                               int32_t *__restrict__ sorted) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  sorted[atomicAdd(fill + cell_of[i], 1)] = i;
+  sorted[atomicAdd(fill + (cell_of[i] >> 3), 1)] = i;
 }
 
-// Particles of each cell in index order (a fixed summation order); the counts are cleared.  One
-// workgroup per cell: the cell's indices are staged in LDS and each is written to its rank (the
-// number of smaller indices; indices are distinct).  A cell of more than kSortCap particles is
-// sorted by one thread.
+// Particles of each cell ordered by (octant, index): a fixed summation order in which
+// consecutive targets of the short-range pass are close together.  The counts are cleared.  One
+// workgroup per cell: the cell's keys (octant, index; distinct) are staged in LDS and each
+// particle is written to its rank (the number of smaller keys).  A cell of more than kSortCap
+// particles is sorted by one thread.
 constexpr int kSortCap = 2048;
 __global__ __launch_bounds__(256) void k_p3m_sort(int32_t ncell, const int32_t *__restrict__ starts,
-                                                  int32_t *__restrict__ sorted, int32_t *__restrict__ counts) {
-  __shared__ int32_t v[kSortCap];
+                                                  int32_t *__restrict__ sorted, int32_t *__restrict__ counts,
+                                                  const int32_t *__restrict__ cell_of) {
+  __shared__ int64_t v[kSortCap];
   const int c = blockIdx.x;
   const int b = starts[c], n = starts[c + 1] - b;
+  auto key = [&](int i) { return ((int64_t)(cell_of[i] & 7) << 32) | (int64_t)i; };
   if (threadIdx.x == 0) counts[c] = 0;
   if (n <= 1) return;   // uniform
   if (n > kSortCap) {
     if (threadIdx.x == 0) {
       for (int k = b + 1; k < b + n; ++k) {
         const int x = sorted[k];
+        const int64_t kx = key(x);
         int j = k - 1;
-        while (j >= b && sorted[j] > x) {
+        while (j >= b && key(sorted[j]) > kx) {
           sorted[j + 1] = sorted[j];
           --j;
         }
@@ -473,13 +485,13 @@ __global__ __launch_bounds__(256) void k_p3m_sort(int32_t ncell, const int32_t *
     }
     return;
   }
-  for (int e = threadIdx.x; e < n; e += blockDim.x) v[e] = sorted[b + e];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) v[e] = key(sorted[b + e]);
   __syncthreads();
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int x = v[e];
+    const int64_t x = v[e];
     int rank = 0;
     for (int k = 0; k < n; ++k) rank += v[k] < x ? 1 : 0;
-    sorted[b + rank] = x;
+    sorted[b + rank] = (int32_t)(x & 0xffffffff);
   }
 }
 
@@ -731,7 +743,8 @@ template <class Real> void launch_p3m(const State<Real> &st, const Phys &ph, con
   hipLaunchKernelGGL((k_p3m_bin<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.cell_of, m.counts);
   hipLaunchKernelGGL(k_p3m_scan, dim3(1), dim3(1024), 0, s, ncell, m.counts, m.starts, m.fill);
   hipLaunchKernelGGL(k_p3m_scatter, dim3(gp), dim3(256), 0, s, ph.N, m.cell_of, m.fill, m.sorted);
-  hipLaunchKernelGGL(k_p3m_sort, dim3((unsigned)ncell), dim3(256), 0, s, ncell, m.starts, m.sorted, m.counts);
+  hipLaunchKernelGGL(k_p3m_sort, dim3((unsigned)ncell), dim3(256), 0, s, ncell, m.starts, m.sorted, m.counts,
+                     m.cell_of);
   hipLaunchKernelGGL((k_p3m_assign<Real>), dim3((unsigned)ncell), dim3(256), 0, s, st, ph, m, m.starts, m.sorted,
                      m.qmesh);
   using T = MeshT<Real>;
