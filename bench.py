@@ -346,8 +346,9 @@ def main():
     args = ap.parse_args()
     p3m_names = args.p3m_workloads.split(",")
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU sharding is described "
-                                   "in DESIGN.md and not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the library has no multi-GPU path "
+                                   "(samples would shard across GPUs with no per-step exchange; a single large "
+                                   "sample would all-gather its source records every step)", "n_gpus": args.gpus}))
         sys.exit(2)
 
     legs = set(args.legs.split(","))
