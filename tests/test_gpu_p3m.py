@@ -81,6 +81,49 @@ def test_p3m_close_to_the_lattice_sum_and_deterministic():
     assert err < 3e-3
 
 
+def lattice_sums_at(x, q, d, L, targets, images):
+    """Raw Coulomb sums of the targets over every source and its x images |n| <= images (the nearest
+    image with the overlap clamp |r| >= d_ij, the others as point charges), in FP64."""
+    S = np.zeros((len(targets), 3))
+    for k, i in enumerate(targets):
+        r = x[i] - x
+        r[:, 0] -= L * np.round(r[:, 0] / L)
+        m = np.arange(x.shape[0]) != i
+        r, qm = r[m], q[m]
+        t2 = r[:, 1] ** 2 + r[:, 2] ** 2
+        dij = 0.5 * (d[i] + d[m])
+        for n in range(-images, images + 1):
+            rx = r[:, 0] + n * L
+            r2 = rx * rx + t2
+            rc2 = np.maximum(r2, dij * dij) if n == 0 else r2
+            w = qm / (np.sqrt(r2) * rc2)
+            S[k] += (w @ rx, w @ r[:, 1], w @ r[:, 2])
+    return S
+
+
+def test_p3m_large_1m_sampled_against_lattice_sum():
+    """The 2^20-particle workload in the P3M configuration the benchmark times (mesh 256 x 128 across,
+    alpha h 0.5, r_max = 3.5 / alpha): 8 sampled targets against the x-periodic lattice sum over all
+    1,048,576 sources (images |n| <= 40), at seed."""
+    w = make_workload("large-1m")
+    f = w.field()
+    cfg = dict(mesh_x=256, mesh_yz=128, alpha_h=0.5, rmax_alpha=3.5)
+    say("case: p3m large-1m vs lattice sum")
+    from paper_2205_04979_amd.depo import Simulation
+    sim = Simulation(dict(w.params, **COULOMB_ONLY), w.offsets, f.shape[:3], real_bytes=4, p3m=cfg)
+    sim.init_field(f)
+    sim.seed(w.sample_params, w.x, w.d, w.qbase)
+    g = sim.read()
+    sim.close()
+    tg = np.sort(np.random.default_rng(4).choice(w.n_particles, 8, replace=False))
+    q = w.sample_params[0, 0] * w.qbase
+    S = lattice_sums_at(g["x"], q, w.d, w.params["L"], tg, 40)
+    a_ref = accel_from_sums(w.params, w.sample_params, w.qbase[tg], w.d[tg], S)
+    err = rel_rms(g["a"][tg], a_ref)
+    say("large-1m sampled rel rms vs lattice sum", err)
+    assert err < 5e-3
+
+
 def test_p3m_single_65k_sampled_against_lattice_sum_and_steps():
     """The 65,536-particle workload with P3M (mesh 128 x 64, alpha h 0.5): sampled targets against the
     lattice sum over all sources, at seed and after 10 steps of the full step with every force on."""
