@@ -696,20 +696,35 @@ int ilog2(int n) {
   return k;
 }
 
+// Which lines of a 3D transform are needed.  The charge occupies iy, iz < nc of the padded mesh,
+// so its forward z pass skips the all-zero lines iy >= nc (the load wrote those zeros); the
+// fields are read back only at iy, iz < nc, so their inverse y pass needs the lines iz < nc and
+// the x pass the lines iy, iz < nc.  The Green's function set-up transforms every line.
+enum class FftLines { kAll, kChargeForward, kFieldInverse };
+
 // 3D transform of the padded mesh: lines along z, y, x.
-template <class T> void fft3d(const P3mDev &m, T *d, int sign, hipStream_t s) {
-  const int64_t P = m.P, nx = m.nx;
-  const int64_t total = nx * P * P;
-  const int lp = ilog2((int)P);
-  // z: points contiguous, line l at l * P
-  hipLaunchKernelGGL(k_fft_lines<T>, dim3((unsigned)(total / kFftLds)), dim3(256), 0, s, d, lp, 0, (int64_t)0, P,
-                     (int64_t)1, sign, 1);
-  // y: line (ix, iz) at ix P^2 + iz, points P apart
-  hipLaunchKernelGGL(k_fft_lines<T>, dim3((unsigned)(total / kFftLds)), dim3(256), 0, s, d, lp, lp, (int64_t)1, P * P,
-                     P, sign, 0);
-  // x: line (iy, iz) at iy P + iz, points P^2 apart
-  hipLaunchKernelGGL(k_fft_lines<T>, dim3((unsigned)(total / kFftLds)), dim3(256), 0, s, d, ilog2((int)nx), 0,
-                     (int64_t)0, (int64_t)1, P * P, sign, 0);
+template <class T> void fft3d(const P3mDev &m, T *d, int sign, FftLines which, hipStream_t s) {
+  const int64_t P = m.P, nx = m.nx, nc = m.nc;
+  const int lp = ilog2((int)P), lx = ilog2((int)nx), lc = ilog2((int)nc);
+  auto grid = [](int64_t points) { return dim3((unsigned)(points / kFftLds)); };
+  if (which == FftLines::kChargeForward)   // z: line (ix, iy < nc) at ix P^2 + iy P, points contiguous
+    hipLaunchKernelGGL(k_fft_lines<T>, grid(nx * nc * P), dim3(256), 0, s, d, lp, lc, P, P * P, (int64_t)1, sign,
+                       1);
+  else   // z: line l at l P, points contiguous
+    hipLaunchKernelGGL(k_fft_lines<T>, grid(nx * P * P), dim3(256), 0, s, d, lp, 0, (int64_t)0, P, (int64_t)1,
+                       sign, 1);
+  if (which == FftLines::kFieldInverse)    // y: line (ix, iz < nc) at ix P^2 + iz, points P apart
+    hipLaunchKernelGGL(k_fft_lines<T>, grid(nx * nc * P), dim3(256), 0, s, d, lp, lc, (int64_t)1, P * P, P, sign,
+                       0);
+  else   // y: line (ix, iz) at ix P^2 + iz, points P apart
+    hipLaunchKernelGGL(k_fft_lines<T>, grid(nx * P * P), dim3(256), 0, s, d, lp, lp, (int64_t)1, P * P, P, sign,
+                       0);
+  if (which == FftLines::kFieldInverse)    // x: line (iy < nc, iz < nc) at iy P + iz, points P^2 apart
+    hipLaunchKernelGGL(k_fft_lines<T>, grid(nc * nc * nx), dim3(256), 0, s, d, lx, lc, (int64_t)1, P, P * P, sign,
+                       0);
+  else   // x: line (iy, iz) at iy P + iz, points P^2 apart
+    hipLaunchKernelGGL(k_fft_lines<T>, grid(nx * P * P), dim3(256), 0, s, d, lx, 0, (int64_t)0, (int64_t)1, P * P,
+                       sign, 0);
 }
 
 }  // namespace
@@ -722,13 +737,13 @@ void p3m_setup_green(const P3mDev &m, double L, int images, bool fp32_mesh, hipS
     double2 *tmp = (double2 *)m.rho;
     for (int c = 0; c < 3; ++c) {
       hipLaunchKernelGGL(k_p3m_green, dim3(g), dim3(256), 0, s, m, L, images, c, tmp, tmp, tmp);
-      fft3d<double2>(m, tmp, -1, s);
+      fft3d<double2>(m, tmp, -1, FftLines::kAll, s);
       hipLaunchKernelGGL(k_p3m_deconv_f32, dim3(g), dim3(256), 0, s, m, tmp, (float2 *)m.ghat[c]);
     }
   } else {
     double2 *gh[3] = {(double2 *)m.ghat[0], (double2 *)m.ghat[1], (double2 *)m.ghat[2]};
     hipLaunchKernelGGL(k_p3m_green, dim3(g), dim3(256), 0, s, m, L, images, -1, gh[0], gh[1], gh[2]);
-    for (int c = 0; c < 3; ++c) fft3d<double2>(m, gh[c], -1, s);
+    for (int c = 0; c < 3; ++c) fft3d<double2>(m, gh[c], -1, FftLines::kAll, s);
     hipLaunchKernelGGL(k_p3m_deconv, dim3(g), dim3(256), 0, s, m, gh[0], gh[1], gh[2]);
   }
   hipLaunchKernelGGL(k_p3m_table, dim3((kSrTable + 256) / 256), dim3(256), 0, s, m, m.table);
@@ -751,14 +766,14 @@ template <class Real> void launch_p3m(const State<Real> &st, const Phys &ph, con
   T *rho = (T *)m.rho, *work = (T *)m.work;
   const T *g0 = (const T *)m.ghat[0], *g1 = (const T *)m.ghat[1], *g2 = (const T *)m.ghat[2];
   hipLaunchKernelGGL(k_p3m_load<T>, dim3(gm), dim3(256), 0, s, m, m.qmesh, rho);
-  fft3d<T>(m, rho, -1, s);
+  fft3d<T>(m, rho, -1, FftLines::kChargeForward, s);
   // E_x + i E_y from one inverse transform, then E_z
   hipLaunchKernelGGL(k_p3m_mul2<T>, dim3(gm), dim3(256), 0, s, m, rho, g0, g1, work);
-  fft3d<T>(m, work, +1, s);
+  fft3d<T>(m, work, +1, FftLines::kFieldInverse, s);
   hipLaunchKernelGGL((k_p3m_interp<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.sorted, work, m.slong,
                      m.slong + ph.N);
   hipLaunchKernelGGL(k_p3m_mul<T>, dim3(gm), dim3(256), 0, s, m, rho, g2, work);
-  fft3d<T>(m, work, +1, s);
+  fft3d<T>(m, work, +1, FftLines::kFieldInverse, s);
   hipLaunchKernelGGL((k_p3m_interp<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.sorted, work,
                      m.slong + 2 * (int64_t)ph.N, (double *)nullptr);
   SrRec<Real> *rec = (SrRec<Real> *)m.rec;
