@@ -29,22 +29,24 @@ def _key(sim) -> str:
 
 
 def autotune(sim, steps: int = 3, cache_path: Optional[str] = None, verbose: bool = False, refine: int = 3,
-             rounds: int = 3):
+             rounds: int = 3, shapes=None):
     """Return (best_shape, {shape: ms per Coulomb launch}) and apply the best shape to ``sim``.
 
-    Every shape is timed over ``steps`` steps; the ``refine`` fastest are then timed again in
-    ``rounds`` round-robin passes (so that clock drift affects them alike) and each keeps its
-    fastest measurement."""
+    Every shape (``shapes``, default: every compiled shape of the precision) is timed over ``steps``
+    steps; the ``refine`` fastest are then timed again in ``rounds`` round-robin passes (so that
+    clock drift affects them alike) and each keeps its fastest measurement."""
     key = _key(sim)
+    custom = shapes is not None   # a caller's own candidate list is neither read from nor written to the cache
     cache = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as fh:
             cache = json.load(fh)
-        if key in cache:
+        if key in cache and not custom:
             best = tuple(cache[key]["best"])
             sim.set_kernel_config(*best)
             return best, {tuple(json.loads(k)): v for k, v in cache[key]["ms"].items()}
-    shapes = FP32_SHAPES + FP32_SYM_SHAPES if sim.real_bytes == 4 else FP64_SHAPES
+    if shapes is None:
+        shapes = FP32_SHAPES + FP32_SYM_SHAPES if sim.real_bytes == 4 else FP64_SHAPES
     blob = sim.state_download()
     times = {}
     for shp in shapes:
@@ -70,7 +72,7 @@ def autotune(sim, steps: int = 3, cache_path: Optional[str] = None, verbose: boo
             times[shp] = min(times[shp], ms)
     best = min(finalists, key=times.get)
     sim.set_kernel_config(*best)
-    if cache_path:
+    if cache_path and not custom:
         cache[key] = {"best": list(best), "ms": {json.dumps(list(k)): v for k, v in times.items()}}
         with open(cache_path, "w") as fh:
             json.dump(cache, fh, indent=1)

@@ -915,7 +915,8 @@ depo_status do_adjoint(depo_ctx *ctx, int n, int ce, const double *hw, double *h
   // below runs only the O(N) kernels
   for (int k = 0; k < n; ++k) {
     if (k % ce == 0) launch_tape_store<Real>(st, pl.ckpt[k / ce], N, false, s);
-    enqueue_step<Real>(ctx, s);
+    // the same step as depo_step (the captured graph, when enabled); the step counter is set below
+    if (depo_status r = run_steps<Real>(ctx, 1, s); r != DEPO_OK) return r;
     if (coul && k % ce != ce - 1 && k != n - 1) HIP_TRY(sums_to_tape((k / ce) * (ce - 1) + k % ce));
   }
   launch_tape_store<Real>(st, pl.fin, N, true, s);
