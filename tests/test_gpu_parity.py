@@ -578,3 +578,56 @@ def test_fp32_large_1m_force_error_compensated_vs_plain():
         say("compensated" if comp else "plain", "max", res[comp].max(), "median", np.median(res[comp]))
     assert res[True].max() < 2e-6
     assert np.median(res[True]) <= np.median(res[False])
+
+
+@pytest.mark.parametrize("real_bytes", [4, 8])
+def test_empty_single_and_pair_samples(real_bytes):
+    """Samples of 0, 1, 2, 0, 65 and 300 particles in one layout (the default pair mode of the
+    precision): every particle's acceleration at seed against the oracle, positions after 5 steps
+    (FP64: round-off; FP32: within 1e-5 R), and per-sample tallies that conserve particles (the empty
+    samples tally nothing and report V_dep = 0)."""
+    w = make_workload("batched-256", n_samples=6, n_lo=100, n_hi=400, field_n=16)
+    f = w.field()
+    sizes = [0, 1, 2, 0, 65, 300]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(off[-1])
+    x, d, q = w.x[:n], w.d[:n], w.qbase[:n]
+    say("case: empty / single / pair samples, sizes", sizes, "fp", 8 * real_bytes)
+    sim, ora = seeded_pair(w.params, f, x, d, q, off, w.sample_params, real_bytes)
+    g = sim.read()
+    tg = np.arange(n)
+    e = force_error(g["a"], ora.a, coulomb_scale(ora, tg))
+    say("force error max", e.max())
+    assert e.max() < (1e-9 if real_bytes == 8 else 1e-5)
+    sim.step(5)
+    ora.step(5)
+    g = sim.read()
+    both = (g["dep_step"] == 0) & ora.alive
+    err = position_error(g["x"][both], ora.x[both], ora.L, ora.R)
+    say("position error max / R", err.max(), "alive in both", int(both.sum()))
+    assert err.max() < (1e-12 if real_bytes == 8 else 1e-5)
+    t = sim.tally()
+    for s, size in enumerate(sizes):
+        assert t[s]["n_alive"] + t[s]["n_dep"] == size, s
+        if size == 0:
+            assert t[s]["n_dep"] == 0 and t[s]["m_alive_dt"] == 0.0 and t[s]["v_dep"] == 0.0
+
+
+@pytest.mark.parametrize("real_bytes", [4, 8])
+def test_layout_without_particles(real_bytes):
+    """A layout whose samples hold no particles at all seeds, steps (graph and direct launches),
+    evaluates forces and tallies zeros."""
+    f = make_workload("plain-1k", n=4, field_n=16).field()
+    p = physical_params(180.0)
+    off = np.array([0, 0, 0], dtype=np.int64)
+    say("case: layout without particles, fp", 8 * real_bytes)
+    sim, _ = seeded_pair(p, f, np.zeros((0, 3)), np.zeros(0), np.zeros(0), off,
+                         np.array([[1.0, 1e-20, 300.0]] * 2), real_bytes, oracle=False)
+    sim.step(2)            # the precision's default pair mode, captured graph
+    for graph in (True, False):
+        sim.set_kernel_config(*((1, 8, 32) if real_bytes == 4 else (1, 4, 16)), use_graph=graph)
+        sim.step(3)
+    sim.eval_accel()
+    t = sim.tally()
+    assert len(t) == 2 and all(x["n_alive"] == 0 and x["n_dep"] == 0 and x["v_dep"] == 0.0 for x in t)
+    assert sim.read()["x"].shape == (0, 3)
