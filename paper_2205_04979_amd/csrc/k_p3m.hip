@@ -144,10 +144,28 @@ __global__ void k_p3m_deconv_f32(P3mDev m, const double2 *__restrict__ g, float2
 // a power of two, so all index arithmetic is shifts and masks.
 constexpr int kFftLog2Lds = 11;
 static_assert((1 << kFftLog2Lds) == kFftLds, "kFftLds is 2^kFftLog2Lds");
-template <class T>
+// Where a pass takes its input (its output always goes to data):
+//  kData     data itself;
+//  kCharge   the fixed-point TSC charge (line l = ix nc + iy of a z pass over iy < nc, point iz: the
+//            node l nc + iz for iz < nc, zero beyond), which it clears for the next step;
+//  kZeroPad  data for points p < nc and zero beyond (a y pass of the charge: iy >= nc is empty);
+//  kMul2     a g1 + i a g2 at the same node: two real fields in one transform (the charge and
+//            both Green's functions are real on the mesh, so the inverse transforms of a g1 and of
+//            a g2 are real and that of a g1 + i a g2 is E1 + i E2);
+//  kMul      a g1 at the same node.
+enum FftLoad : int { kData, kCharge, kZeroPad, kMul2, kMul };
+
+struct FftSrc {
+  const void *a, *g1, *g2;          // kMul2 / kMul operands (mesh type)
+  unsigned long long *qmesh;        // kCharge: fixed-point charge, nx x nc x nc
+  const double *q_scale;            // kCharge: fixed-point units per unit of scaled charge
+  int nc;                           // kCharge / kZeroPad: populated extent across the section
+};
+
+template <class T, int LOAD>
 __global__ __launch_bounds__(256) void k_fft_lines(T *__restrict__ data, int log2n, int log2inner,
                                                    int64_t inner_stride, int64_t outer_stride, int64_t point_stride,
-                                                   int sign, int points_contiguous) {
+                                                   int sign, int points_contiguous, FftSrc src) {
   __shared__ T buf[kFftLds];
   __shared__ T tw[kFftLds / 2];
   const int n = 1 << log2n;
@@ -168,7 +186,30 @@ __global__ __launch_bounds__(256) void k_fft_lines(T *__restrict__ data, int log
     const int line = points_contiguous ? e >> log2n : e & lmask;
     const int p = points_contiguous ? e & pmask : e >> log2lpw;
     const int rev = (int)(__brev((unsigned)p) >> (32 - log2n));
-    buf[(line << log2n) + rev] = data[addr(line, p)];
+    T v;
+    if constexpr (LOAD == kData) {
+      v = data[addr(line, p)];
+    } else if constexpr (LOAD == kCharge) {
+      v = cplx<T>(0.0, 0.0);
+      if (p < src.nc) {
+        const int64_t o = (l0 + line) * src.nc + p;
+        v = cplx<T>((double)(long long)src.qmesh[o] / *src.q_scale, 0.0);
+        src.qmesh[o] = 0ull;
+      }
+    } else if constexpr (LOAD == kZeroPad) {
+      v = p < src.nc ? data[addr(line, p)] : cplx<T>(0.0, 0.0);
+    } else {
+      const int64_t o = addr(line, p);
+      const T a = ((const T *)src.a)[o];
+      const T pp = cmul(a, ((const T *)src.g1)[o]);
+      if constexpr (LOAD == kMul2) {
+        const T qq = cmul(a, ((const T *)src.g2)[o]);
+        v = T{pp.x - qq.y, pp.y + qq.x};
+      } else {
+        v = pp;
+      }
+    }
+    buf[(line << log2n) + rev] = v;
   }
   __syncthreads();
   // radix-2 stages lg and lg + 1 fused: each group of 4 points (i0, i0 + h, i0 + 2h, i0 + 3h),
@@ -317,41 +358,6 @@ __global__ __launch_bounds__(256) void k_p3m_assign(State<Real> st, Phys ph, P3m
     jx = jx < 0 ? jx + m.nx : (jx >= m.nx ? jx - m.nx : jx);
     atomicAdd(qmesh + ((int64_t)jx * m.nc + (lo[1] - 1 + b)) * m.nc + (lo[2] - 1 + c), v);
   }
-}
-
-// Fixed-point charges into the zero-padded complex mesh (every node written); the charge mesh is cleared.
-template <class T>
-__global__ void k_p3m_load(P3mDev m, unsigned long long *__restrict__ qmesh, T *__restrict__ rho) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)m.nx * m.P * m.P;
-  if (e >= total) return;
-  const int iz = (int)(e % m.P), iy = (int)((e / m.P) % m.P), ix = (int)(e / ((int64_t)m.P * m.P));
-  double v = 0.0;
-  if (iy < m.nc && iz < m.nc) {
-    const int64_t o = ((int64_t)ix * m.nc + iy) * m.nc + iz;
-    v = (double)(long long)qmesh[o] / *m.q_scale;
-    qmesh[o] = 0ull;
-  }
-  rho[e] = cplx<T>(v, 0.0);
-}
-
-template <class T>
-__global__ void k_p3m_mul(P3mDev m, const T *__restrict__ a, const T *__restrict__ g, T *__restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)m.nx * m.P * m.P) return;
-  out[e] = cmul(a[e], g[e]);
-}
-
-// Two real fields in one transform: out = a g1 + i a g2.  The charge and both Green's functions
-// are real on the mesh, so the inverse transform of a g1 and of a g2 are real, and the inverse
-// transform of out is E1 + i E2.
-template <class T>
-__global__ void k_p3m_mul2(P3mDev m, const T *__restrict__ a, const T *__restrict__ g1, const T *__restrict__ g2,
-                           T *__restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)m.nx * m.P * m.P) return;
-  const T p = cmul(a[e], g1[e]), q = cmul(a[e], g2[e]);
-  out[e] = T{p.x - q.y, p.y + q.x};
 }
 
 // TSC interpolation of the unnormalised inverse transform: its real part to out_re and, when
@@ -697,34 +703,47 @@ int ilog2(int n) {
 }
 
 // Which lines of a 3D transform are needed.  The charge occupies iy, iz < nc of the padded mesh,
-// so its forward z pass skips the all-zero lines iy >= nc (the load wrote those zeros); the
-// fields are read back only at iy, iz < nc, so their inverse y pass needs the lines iz < nc and
-// the x pass the lines iy, iz < nc.  The Green's function set-up transforms every line.
+// so its forward z pass reads the fixed-point charge directly (the lines iy >= nc are all zero and
+// are not stored: the y pass takes them as zero); the fields are read back only at iy, iz < nc,
+// so their inverse y pass needs the lines iz < nc and the x pass the lines iy, iz < nc, and their
+// z pass forms the spectral product as it loads.  The Green's function set-up transforms every
+// line of data in place.
 enum class FftLines { kAll, kChargeForward, kFieldInverse };
 
-// 3D transform of the padded mesh: lines along z, y, x.
-template <class T> void fft3d(const P3mDev &m, T *d, int sign, FftLines which, hipStream_t s) {
+// 3D transform of the padded mesh: lines along z, y, x.  first: the load mode of the z pass
+// (kData, kCharge for the charge, kMul2 / kMul for the fields).
+template <class T> void fft3d(const P3mDev &m, T *d, int sign, FftLines which, int first, const FftSrc &src,
+                              hipStream_t s) {
   const int64_t P = m.P, nx = m.nx, nc = m.nc;
   const int lp = ilog2((int)P), lx = ilog2((int)nx), lc = ilog2((int)nc);
   auto grid = [](int64_t points) { return dim3((unsigned)(points / kFftLds)); };
   if (which == FftLines::kChargeForward)   // z: line (ix, iy < nc) at ix P^2 + iy P, points contiguous
-    hipLaunchKernelGGL(k_fft_lines<T>, grid(nx * nc * P), dim3(256), 0, s, d, lp, lc, P, P * P, (int64_t)1, sign,
-                       1);
-  else   // z: line l at l P, points contiguous
-    hipLaunchKernelGGL(k_fft_lines<T>, grid(nx * P * P), dim3(256), 0, s, d, lp, 0, (int64_t)0, P, (int64_t)1,
-                       sign, 1);
+    hipLaunchKernelGGL((k_fft_lines<T, kCharge>), grid(nx * nc * P), dim3(256), 0, s, d, lp, lc, P, P * P,
+                       (int64_t)1, sign, 1, src);
+  else if (first == kMul2)   // z: line l at l P, points contiguous
+    hipLaunchKernelGGL((k_fft_lines<T, kMul2>), grid(nx * P * P), dim3(256), 0, s, d, lp, 0, (int64_t)0, P,
+                       (int64_t)1, sign, 1, src);
+  else if (first == kMul)
+    hipLaunchKernelGGL((k_fft_lines<T, kMul>), grid(nx * P * P), dim3(256), 0, s, d, lp, 0, (int64_t)0, P,
+                       (int64_t)1, sign, 1, src);
+  else
+    hipLaunchKernelGGL((k_fft_lines<T, kData>), grid(nx * P * P), dim3(256), 0, s, d, lp, 0, (int64_t)0, P,
+                       (int64_t)1, sign, 1, src);
   if (which == FftLines::kFieldInverse)    // y: line (ix, iz < nc) at ix P^2 + iz, points P apart
-    hipLaunchKernelGGL(k_fft_lines<T>, grid(nx * nc * P), dim3(256), 0, s, d, lp, lc, (int64_t)1, P * P, P, sign,
-                       0);
+    hipLaunchKernelGGL((k_fft_lines<T, kData>), grid(nx * nc * P), dim3(256), 0, s, d, lp, lc, (int64_t)1, P * P,
+                       P, sign, 0, src);
+  else if (which == FftLines::kChargeForward)   // y: line (ix, iz), points iy >= nc taken as zero
+    hipLaunchKernelGGL((k_fft_lines<T, kZeroPad>), grid(nx * P * P), dim3(256), 0, s, d, lp, lp, (int64_t)1,
+                       P * P, P, sign, 0, src);
   else   // y: line (ix, iz) at ix P^2 + iz, points P apart
-    hipLaunchKernelGGL(k_fft_lines<T>, grid(nx * P * P), dim3(256), 0, s, d, lp, lp, (int64_t)1, P * P, P, sign,
-                       0);
+    hipLaunchKernelGGL((k_fft_lines<T, kData>), grid(nx * P * P), dim3(256), 0, s, d, lp, lp, (int64_t)1, P * P,
+                       P, sign, 0, src);
   if (which == FftLines::kFieldInverse)    // x: line (iy < nc, iz < nc) at iy P + iz, points P^2 apart
-    hipLaunchKernelGGL(k_fft_lines<T>, grid(nc * nc * nx), dim3(256), 0, s, d, lx, lc, (int64_t)1, P, P * P, sign,
-                       0);
+    hipLaunchKernelGGL((k_fft_lines<T, kData>), grid(nc * nc * nx), dim3(256), 0, s, d, lx, lc, (int64_t)1, P,
+                       P * P, sign, 0, src);
   else   // x: line (iy, iz) at iy P + iz, points P^2 apart
-    hipLaunchKernelGGL(k_fft_lines<T>, grid(nx * P * P), dim3(256), 0, s, d, lx, 0, (int64_t)0, (int64_t)1, P * P,
-                       sign, 0);
+    hipLaunchKernelGGL((k_fft_lines<T, kData>), grid(nx * P * P), dim3(256), 0, s, d, lx, 0, (int64_t)0,
+                       (int64_t)1, P * P, sign, 0, src);
 }
 
 }  // namespace
@@ -737,13 +756,13 @@ void p3m_setup_green(const P3mDev &m, double L, int images, bool fp32_mesh, hipS
     double2 *tmp = (double2 *)m.rho;
     for (int c = 0; c < 3; ++c) {
       hipLaunchKernelGGL(k_p3m_green, dim3(g), dim3(256), 0, s, m, L, images, c, tmp, tmp, tmp);
-      fft3d<double2>(m, tmp, -1, FftLines::kAll, s);
+      fft3d<double2>(m, tmp, -1, FftLines::kAll, kData, FftSrc{}, s);
       hipLaunchKernelGGL(k_p3m_deconv_f32, dim3(g), dim3(256), 0, s, m, tmp, (float2 *)m.ghat[c]);
     }
   } else {
     double2 *gh[3] = {(double2 *)m.ghat[0], (double2 *)m.ghat[1], (double2 *)m.ghat[2]};
     hipLaunchKernelGGL(k_p3m_green, dim3(g), dim3(256), 0, s, m, L, images, -1, gh[0], gh[1], gh[2]);
-    for (int c = 0; c < 3; ++c) fft3d<double2>(m, gh[c], -1, FftLines::kAll, s);
+    for (int c = 0; c < 3; ++c) fft3d<double2>(m, gh[c], -1, FftLines::kAll, kData, FftSrc{}, s);
     hipLaunchKernelGGL(k_p3m_deconv, dim3(g), dim3(256), 0, s, m, gh[0], gh[1], gh[2]);
   }
   hipLaunchKernelGGL(k_p3m_table, dim3((kSrTable + 256) / 256), dim3(256), 0, s, m, m.table);
@@ -751,8 +770,7 @@ void p3m_setup_green(const P3mDev &m, double L, int images, bool fp32_mesh, hipS
 
 template <class Real> void launch_p3m(const State<Real> &st, const Phys &ph, const P3mDev &m, hipStream_t s) {
   if (ph.N <= 0) return;
-  const int64_t total = (int64_t)m.nx * m.P * m.P;
-  const unsigned gm = (unsigned)((total + 255) / 256), gp = (unsigned)((ph.N + 255) / 256);
+  const unsigned gp = (unsigned)((ph.N + 255) / 256);
   // short-range cells first: the mesh passes also walk the particles in cell order
   const int ncell = m.ncx * m.ncy * m.ncy;
   hipLaunchKernelGGL((k_p3m_bin<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.cell_of, m.counts);
@@ -765,15 +783,14 @@ template <class Real> void launch_p3m(const State<Real> &st, const Phys &ph, con
   using T = MeshT<Real>;
   T *rho = (T *)m.rho, *work = (T *)m.work;
   const T *g0 = (const T *)m.ghat[0], *g1 = (const T *)m.ghat[1], *g2 = (const T *)m.ghat[2];
-  hipLaunchKernelGGL(k_p3m_load<T>, dim3(gm), dim3(256), 0, s, m, m.qmesh, rho);
-  fft3d<T>(m, rho, -1, FftLines::kChargeForward, s);
-  // E_x + i E_y from one inverse transform, then E_z
-  hipLaunchKernelGGL(k_p3m_mul2<T>, dim3(gm), dim3(256), 0, s, m, rho, g0, g1, work);
-  fft3d<T>(m, work, +1, FftLines::kFieldInverse, s);
+  // forward transform of the charge, read from the fixed-point mesh by the first pass
+  fft3d<T>(m, rho, -1, FftLines::kChargeForward, kCharge, FftSrc{nullptr, nullptr, nullptr, m.qmesh, m.q_scale, m.nc},
+           s);
+  // E_x + i E_y from one inverse transform, then E_z; the first pass forms the spectral product
+  fft3d<T>(m, work, +1, FftLines::kFieldInverse, kMul2, FftSrc{rho, g0, g1, nullptr, nullptr, m.nc}, s);
   hipLaunchKernelGGL((k_p3m_interp<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.sorted, work, m.slong,
                      m.slong + ph.N);
-  hipLaunchKernelGGL(k_p3m_mul<T>, dim3(gm), dim3(256), 0, s, m, rho, g2, work);
-  fft3d<T>(m, work, +1, FftLines::kFieldInverse, s);
+  fft3d<T>(m, work, +1, FftLines::kFieldInverse, kMul, FftSrc{rho, g2, nullptr, nullptr, nullptr, m.nc}, s);
   hipLaunchKernelGGL((k_p3m_interp<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.sorted, work,
                      m.slong + 2 * (int64_t)ph.N, (double *)nullptr);
   SrRec<Real> *rec = (SrRec<Real> *)m.rec;
