@@ -515,8 +515,16 @@ __global__ void k_p3m_records(State<Real> st, Phys ph, const int32_t *__restrict
   const int i = sorted[k];
   SrRec<Real> r;
   r.x = st.px[i];
-  r.y = st.py[i];
-  r.z = st.pz[i];
+  if constexpr (sizeof(Real) == 4) {
+    // FP32 form: y and z as floats in y/z position quanta (bit patterns in the Pos fields), so that
+    // the short-range body takes their differences with one subtraction
+    using SPos = typename std::make_signed<typename Prec<Real>::Pos>::type;
+    r.y = __float_as_uint((float)(SPos)st.py[i]);
+    r.z = __float_as_uint((float)(SPos)st.pz[i]);
+  } else {
+    r.y = st.py[i];
+    r.z = st.pz[i];
+  }
   r.q = st.js[i].q;
   // FP32: the radius in y/z position quanta (the short-range body works in those units);
   // FP64: the diameter in metres
@@ -633,11 +641,12 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
       for (int e = slice; e < n; e += S) {
         const SrRec<Real> s = src[e];
         if constexpr (sizeof(Real) == 4) {
-          // y/z quanta; r2 floored so that r = 0 (the target itself) gives a finite f times dx = 0
+          // y/z quanta; r2 carries 1e-20 (below the rounding of any r2 >= 1, i.e. of any two distinct
+          // positions) so that r = 0 (the target itself) gives a finite f times dx = 0
           const float dx = (float)(int32_t)(me.x - s.x) * kx;
-          const float dy = (float)((int32_t)me.y - (int32_t)s.y);
-          const float dz = (float)((int32_t)me.z - (int32_t)s.z);
-          const float r2 = fmaxf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), 1e-20f);
+          const float dy = __uint_as_float(me.y) - __uint_as_float(s.y);
+          const float dz = __uint_as_float(me.z) - __uint_as_float(s.z);
+          const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, 1e-20f)));
           if (!__builtin_amdgcn_ballot_w64(r2 < skip2q)) continue;   // no active lane within r_max
           const float inv = __builtin_amdgcn_rsqf(r2);
           const float r = r2 * inv;

@@ -47,7 +47,8 @@ def rel_rms(a, ref):
 def test_p3m_matches_oracle_p3m(real_bytes):
     """Same algorithm, same inputs (the GPU's own fixed-point positions): the FP64 form agrees with the
     FP64 oracle to rounding; the FP32 form adds the rounding of its FP32 scaled charges, its complex
-    FP32 mesh and FFTs (Green's function built in FP64) and its result."""
+    FP32 mesh and FFTs (Green's function built in FP64), its short-range source records (y and z as
+    floats in position quanta, spacing up to 64 quanta near the wall) and its result."""
     w = make_workload("single-65k", n=600, field_n=16, **COULOMB_ONLY)
     f = w.field()
     cfg = dict(mesh_x=32, mesh_yz=16, alpha_h=0.5, rmax_alpha=3.5)
