@@ -172,6 +172,27 @@ def test_adjoint_host_validation(depo):
     assert L.depo_adjoint(ctx._h, 10, 5, w, g, C.c_void_p(256), 1 << 30, None) == depo.E_STATE  # not seeded
 
 
+def test_adjoint_workspace_holds_the_coulomb_tape(depo):
+    """With Coulomb on, the adjoint workspace also holds the raw pair sums (3 FP32 values per particle)
+    of the n_steps - ceil(n_steps / ckpt_every) steps the reverse sweep recomputes, so that it never
+    reruns the pair kernel; with Coulomb off it holds none."""
+    L = depo.lib()
+    N = 3000
+    on = depo.Context(physical_params(soft_tally=True), 4)
+    off = depo.Context(physical_params(soft_tally=True, coulomb=False), 4)
+    for c in (on, off):
+        c.set_layout([0, 1000, N], 16, 16, 16)
+    n = C.c_size_t()
+    for steps, ce in ((100, 10), (100, 1), (37, 5), (1, 1)):
+        K = -(-steps // ce)
+        assert L.depo_adjoint_workspace_bytes(on._h, steps, ce, C.byref(n)) == depo.OK
+        a = n.value
+        assert L.depo_adjoint_workspace_bytes(off._h, steps, ce, C.byref(n)) == depo.OK
+        b = n.value
+        tape = (steps - K) * 3 * N * 4
+        assert a - b == -(-tape // 256) * 256, (steps, ce)
+
+
 def test_lf_solve_host_validation(depo):
     """The low-fidelity entry point checks its parameters and sizes before touching the device."""
     L = depo.lib()
