@@ -85,6 +85,47 @@ def cpu_baseline(w, field, n_targets: int):
                 seconds=wall)
 
 
+def _force_chunk(targets):
+    _SIM.accelerations(np.asarray(targets), chunk=8)   # 8 x 2^20 pair arrays per pass (~0.2 GB each)
+    return len(targets)
+
+
+def oracle_timings() -> dict:
+    """The FP64 oracle on the host cores, as context for the GPU figures: the 1,024-particle FP64
+    workload run in full (200 steps, one process: each step is one vectorised pass over all pairs),
+    and the 2^20-particle force check (4,096 targets, index = 0 mod 256, over all sources, on a pool of
+    processes)."""
+    global _SIM
+    from oracle.sim import OracleSim
+    from synthetic import make_workload
+    cores = min(16, len(os.sched_getaffinity(0)))
+    out = {"cores": cores}
+    w = make_workload("plain-1k")
+    f = w.field()
+    sim = OracleSim(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params)
+    t0 = time.perf_counter()
+    sim.step(w.steps)
+    wall = time.perf_counter() - t0
+    n = w.n_particles
+    out["plain-1k"] = {"steps": w.steps, "seconds": round(wall, 2), "particle_steps_per_s": round(n * w.steps / wall, 1),
+                       "ordered_pairs_per_s": round(n * (n - 1) * w.steps / wall, 1), "processes": 1}
+    log(f"[bench] oracle plain-1k: {out['plain-1k']}")
+    w = make_workload("large-1m")
+    f = w.field()
+    _SIM = OracleSim(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, evaluate=False)
+    targets = np.arange(0, w.n_particles, 256)
+    chunks = np.array_split(targets, cores * 4)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        pool.map(_force_chunk, chunks)
+    wall = time.perf_counter() - t0
+    out["large-1m force check"] = {"targets": int(targets.size), "sources": w.n_particles, "seconds": round(wall, 2),
+                                   "ordered_pairs_per_s": round(targets.size * (w.n_particles - 1) / wall, 1),
+                                   "processes": cores}
+    log(f"[bench] oracle large-1m force check: {out['large-1m force check']}")
+    return out
+
+
 def kernel_source_digest(name: str) -> str:
     import hashlib
     src = os.path.join(ROOT, "paper_2205_04979_amd", "csrc", name)
@@ -346,6 +387,9 @@ def main():
     ap.add_argument("--p3m-workloads", default=",".join(P3M_CONFIGS),
                     help="workloads of the p3m leg (comma-separated)")
     ap.add_argument("--p3m-steps", type=int, default=5, help="steps timed per workload in the p3m leg")
+    ap.add_argument("--oracle-timings", action="store_true",
+                    help="only time the FP64 oracle on the host cores (plain-1k in full, the large-1m force "
+                         "check); no GPU")
     args = ap.parse_args()
     p3m_names = args.p3m_workloads.split(",")
     if args.gpus != 1:
@@ -353,6 +397,9 @@ def main():
                                    "(samples would shard across GPUs with no per-step exchange; a single large "
                                    "sample would all-gather its source records every step)", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.oracle_timings:
+        print(json.dumps({"oracle_timings": oracle_timings()}), flush=True)
+        return
 
     legs = set(args.legs.split(","))
     if "single" not in legs:
