@@ -281,6 +281,36 @@ def rebound_run() -> dict:
     return res
 
 
+def plain_run() -> dict:
+    """The 1,024-particle workload in the FP64 form (plain sums), run in full: 200 steps by graph
+    replay.  Small enough that launch latency, not arithmetic, sets the time."""
+    import torch
+    from paper_2205_04979_amd.depo import Simulation
+    from synthetic import make_workload
+    w = make_workload("plain-1k")
+    field = w.field()
+    sim = Simulation(w.params, w.offsets, field.shape[:3], real_bytes=8, device="cuda:0")
+    sim.init_field(field)
+    sim.seed(w.sample_params, w.x, w.d, w.qbase)
+    sim.step(w.steps)                 # warm-up run (graph capture, clocks)
+    sim.seed(w.sample_params, w.x, w.d, w.qbase)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(w.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ph = sim.step_timed(20)
+    res = {"workload": w.name, "particles": w.n_particles, "steps": w.steps, "dtype": "f64",
+           "wall_s": round(wall, 5), "ms_per_step": round(1e3 * wall / w.steps, 4),
+           "particle_steps_per_s": round(w.n_particles * w.steps / wall, 1),
+           "coulomb_ms_per_step": round(ph["coulomb"] / 20, 4)}
+    log(f"[bench] plain: {res}")
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return res
+
+
 def lf_run() -> dict:
     """The low-fidelity model (Appendix B) over the LF-only Monte Carlo budget of Table 3 at p = 36:
     25,920 particle classes (d in {1.6, 5, 16} um, xi ~ U[0, 0.1], zeta ~ U[0, 1]) per launch."""
@@ -378,8 +408,9 @@ def main():
                     help="particles of the workload the CPU oracle steps once (capped at the workload size)")
     ap.add_argument("--kernel", default=None, help="pair-kernel shape ipl,waves,block (skips autotuning)")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--legs", default="single,batched,adjoint,rebound,lf,p3m",
-                    help="which measurements to run: single (the headline), batched, adjoint, rebound, lf, p3m")
+    ap.add_argument("--legs", default="single,batched,adjoint,rebound,plain,lf,p3m",
+                    help="which measurements to run: single (the headline), batched, adjoint, rebound, plain, lf, "
+                         "p3m")
     ap.add_argument("--secondary-steps", type=int, default=100,
                     help="steps timed for the batched Monte Carlo workload (0 disables it)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -413,6 +444,8 @@ def main():
             out["adjoint"] = adjoint_run()
         if "rebound" in legs:
             out["rebound"] = rebound_run()
+        if "plain" in legs:
+            out["plain"] = plain_run()
         if "lf" in legs:
             out["lf"] = lf_run()
         if "p3m" in legs:
@@ -515,6 +548,8 @@ def main():
             out["adjoint"] = adjoint_run()
         if "rebound" in legs:
             out["rebound"] = rebound_run()
+        if "plain" in legs:
+            out["plain"] = plain_run()
         if "lf" in legs:
             out["lf"] = lf_run()
         if "p3m" in legs:
