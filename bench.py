@@ -292,6 +292,8 @@ def plain_run() -> dict:
     sim = Simulation(w.params, w.offsets, field.shape[:3], real_bytes=8, device="cuda:0")
     sim.init_field(field)
     sim.seed(w.sample_params, w.x, w.d, w.qbase)
+    from paper_2205_04979_amd.autotune import autotune
+    shape, tune = autotune(sim, steps=5)
     sim.step(w.steps)                 # warm-up run (graph capture, clocks)
     sim.seed(w.sample_params, w.x, w.d, w.qbase)
     torch.cuda.synchronize()
@@ -303,7 +305,8 @@ def plain_run() -> dict:
     res = {"workload": w.name, "particles": w.n_particles, "steps": w.steps, "dtype": "f64",
            "wall_s": round(wall, 5), "ms_per_step": round(1e3 * wall / w.steps, 4),
            "particle_steps_per_s": round(w.n_particles * w.steps / wall, 1),
-           "coulomb_ms_per_step": round(ph["coulomb"] / 20, 4)}
+           "coulomb_ms_per_step": round(ph["coulomb"] / 20, 4), "pair_kernel_shape": list(shape),
+           "autotune_ms": {",".join(map(str, k)): round(v, 4) for k, v in tune.items()}}
     log(f"[bench] plain: {res}")
     sim.close()
     del sim

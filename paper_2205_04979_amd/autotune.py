@@ -19,7 +19,7 @@ FP32_SHAPES = [(1, 4, 32), (1, 8, 32), (1, 16, 32), (2, 4, 32), (2, 8, 32), (2, 
 # symmetric pair kernel (mode 2): (targets per lane, waves, 64-source rounds, 2); 64 IPL W targets per item
 FP32_SYM_SHAPES = [(1, 4, 64, 2), (1, 8, 64, 2), (2, 2, 64, 2), (2, 4, 64, 2), (4, 1, 64, 2), (4, 2, 64, 2),
                    (4, 4, 64, 2), (8, 1, 64, 2)]
-FP64_SHAPES = [(1, 4, 16), (1, 8, 16), (2, 4, 16)]
+FP64_SHAPES = [(1, 4, 16), (1, 8, 16), (2, 4, 16), (1, 16, 16)]
 
 
 def _key(sim) -> str:

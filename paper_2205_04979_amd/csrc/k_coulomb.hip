@@ -194,7 +194,8 @@ int coulomb_tile_targets(const CoulombConfig &cfg) { return 64 * cfg.ipl; }
   X(float, 1, 8, 64, true, true) X(float, 1, 16, 64, true, true) X(float, 2, 8, 64, true, true)             \
   X(float, 2, 16, 64, true, true) X(float, 1, 4, 64, true, true)                                            \
   X(float, 1, 16, 32, false, false)                                                                         \
-  X(double, 1, 4, 16, false, false) X(double, 1, 8, 16, false, false) X(double, 2, 4, 16, false, false)
+  X(double, 1, 4, 16, false, false) X(double, 1, 8, 16, false, false) X(double, 2, 4, 16, false, false)           \
+  X(double, 1, 16, 16, false, false)
 
 bool coulomb_config_supported(int real_bytes, const CoulombConfig &cfg) {
 #define X(R, I, W, B, K, P) \

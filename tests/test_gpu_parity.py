@@ -403,6 +403,22 @@ def test_fp32_kernel_shapes_agree(cfg):
     assert e.max() < 1e-5
 
 
+@pytest.mark.parametrize("cfg", [(1, 4, 16), (1, 8, 16), (2, 4, 16), (1, 16, 16)])
+def test_fp64_kernel_shapes_agree(cfg):
+    """Every compiled FP64 pair-kernel shape (3,000 particles: 47 tiles of 64 targets, ragged last
+    tile; 4 to 16 waves splitting the sources) gives the oracle's forces to FP64 rounding."""
+    w = make_workload("single-65k", n=3000, field_n=32)
+    f = w.field()
+    say("case: fp64 pair-kernel shape", cfg)
+    sim, ora = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 8)
+    sim.set_kernel_config(*cfg)
+    sim.eval_accel()
+    g = sim.read()
+    e = force_error(g["a"], ora.a, coulomb_scale(ora, np.arange(w.n_particles)))
+    say("force error max", e.max())
+    assert e.max() < 1e-9
+
+
 def test_nonfinite_is_reported():
     """A non-finite input velocity is flagged on the device and reported by the next synchronising call."""
     from paper_2205_04979_amd.depo import DepoError, E_NONFINITE
