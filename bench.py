@@ -306,7 +306,7 @@ def plain_run() -> dict:
            "wall_s": round(wall, 5), "ms_per_step": round(1e3 * wall / w.steps, 4),
            "particle_steps_per_s": round(w.n_particles * w.steps / wall, 1),
            "coulomb_ms_per_step": round(ph["coulomb"] / 20, 4), "pair_kernel_shape": list(shape),
-           "autotune_ms": {",".join(map(str, k)): round(v, 4) for k, v in tune.items()}}
+           "autotune_ms_per_step": {",".join(map(str, k)): round(v, 4) for k, v in tune.items()}}
     log(f"[bench] plain: {res}")
     sim.close()
     del sim
@@ -482,8 +482,9 @@ def main():
         shape = tuple(int(v) for v in args.kernel.split(","))
     elif not args.no_autotune:
         from paper_2205_04979_amd.autotune import autotune
-        shape, tune = autotune(sim, steps=3)
-        log(f"[bench] autotuned pair kernel: {shape} " + ", ".join(f"{k}:{v:.3f}ms" for k, v in tune.items()))
+        shape, tune = autotune(sim, steps=10)
+        log(f"[bench] autotuned pair kernel (ms per step): {shape} " +
+            ", ".join(f"{k}:{v:.3f}ms" for k, v in tune.items()))
     else:
         shape = (4, 2, 64, 2)          # the library default in FP32
     if args.copy_probe_mb:
@@ -539,7 +540,7 @@ def main():
         "config": {"workload": w.name, "particles": N, "samples": w.n_samples,
                    "field": f"{w.field_n}^3", "forces": "drag+coulomb+contact+vdw+wall",
                    "alive_at_end": int(n_alive), "pair_kernel_shape": list(shape),
-                   "autotune_ms": None if tune is None else {",".join(map(str, k)): round(v, 4) for k, v in tune.items()}, "ms_per_step_direct_launch_with_events": round(1e3 * wall_phases / p_steps, 5),
+                   "autotune_ms_per_step": None if tune is None else {",".join(map(str, k)): round(v, 4) for k, v in tune.items()}, "ms_per_step_direct_launch_with_events": round(1e3 * wall_phases / p_steps, 5),
                    "phase_ms_per_step": {k: round(v / p_steps, 5) for k, v in phase_ms.items()},
                    "phase_steps": p_steps},
         "roofline": roofline,
