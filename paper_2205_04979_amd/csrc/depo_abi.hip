@@ -184,7 +184,7 @@ size_t carve(depo_ctx *ctx, char *base, State<Real> &st) {
     m.fill = (int32_t *)take(ncell * 4);
     m.sorted = (int32_t *)take(N * 4);
     m.rec = take(N * 5 * sizeof(typename Prec<Real>::Pos));
-    m.table = (float2 *)take(4097 * sizeof(float2));   // kSrTable intervals + the terminating (0, 0)
+    m.table = (float2 *)take(2049 * sizeof(float2));   // 2,048 intervals + the terminating (0, 0)
     ctx->p3m_qscale = (double *)take(64);
     m.q_scale = ctx->p3m_qscale;
   }

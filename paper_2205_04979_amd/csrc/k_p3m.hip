@@ -533,18 +533,22 @@ __global__ void k_p3m_records(State<Real> st, Phys ph, const int32_t *__restrict
 }
 
 constexpr int kSrLds = 65536;    // bytes of LDS for staged neighbour records (FP64 form)
-constexpr int kSrLdsF32 = 40960; // the same for the FP32 form, which also holds the profile table
+// the same for the FP32 form, which also holds the profile table: 28,000 B of records + 16.4 KB
+// of table + 6 KB of partial sums keep a workgroup within a third of the 160 KB LDS, so three
+// workgroups (24 waves) share a CU
+constexpr int kSrLdsF32 = 28000;
 constexpr int kSrWaves = 8;      // waves per cell
 constexpr int kSrLanes = 64 * kSrWaves;
 constexpr int kSrMaxSlices = 32; // at most this many threads share one target
-constexpr int kSrTable = 4096;   // intervals of the tabulated short-range profile (FP32 form)
+constexpr int kSrTable = 2048;   // intervals of the tabulated short-range profile (FP32 form)
 
 // Short-range force profile g(s) = erfc(s) + (2 s / sqrt(pi)) exp(-s^2), s = alpha r, so that the
 // short-range force of a non-overlapping pair is q g(alpha r) r_vec / r^3; tabulated on
 // [0, alpha r_max] in kSrTable intervals as (g at the interval start, increment over the
 // interval) for linear interpolation in the table coordinate u = kSrTable r / r_max
-// (interpolation error below 1e-7 of the pair force: |g''| < 1.2 and the step is
-// alpha r_max / kSrTable); entry kSrTable is (0, 0): pairs at or beyond r_max get nothing.
+// (interpolation error at most h^2 |g''| / 8 of the pair force with |g''| < 1.2 and the step
+// h = alpha r_max / kSrTable: 4.4e-7 at alpha r_max = 3.5); entry kSrTable is (0, 0): pairs at or
+// beyond r_max get nothing.
 __global__ void k_p3m_table(P3mDev m, float2 *__restrict__ tab) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k > kSrTable) return;
@@ -573,7 +577,7 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
                                                              const float2 *__restrict__ tab) {
   using Pos = typename Prec<Real>::Pos;
   using SPos = typename std::make_signed<Pos>::type;
-  // FP32: 40 KB of staged records + the 32 KB profile table in LDS (two workgroups per CU)
+  // FP32: 28 KB of staged records + the 16 KB profile table in LDS (three workgroups per CU)
   constexpr int CAP = (sizeof(Real) == 4 ? kSrLdsF32 : kSrLds) / sizeof(SrRec<Real>);
   __shared__ SrRec<Real> src[CAP];
   __shared__ float2 stab[sizeof(Real) == 4 ? kSrTable + 1 : 1];

@@ -55,7 +55,7 @@ struct P3mDev {
   double *slong;          // [3][N] long-range part at the particles [1/m^2]
   int32_t *cell_of, *counts, *starts, *fill, *sorted;   // short-range cell list
   void *rec;              // cell-sorted source records of the short-range pass (N records)
-  float2 *table;          // tabulated short-range profile (FP32 form), 4096 intervals + (0, 0)
+  float2 *table;          // tabulated short-range profile (FP32 form), 2048 intervals + (0, 0)
 };
 void p3m_setup_green(const P3mDev &m, double L, int images, bool fp32_mesh, hipStream_t s);
 template <class Real> void launch_p3m(const State<Real> &st, const Phys &ph, const P3mDev &m, hipStream_t s);
