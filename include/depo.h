@@ -183,9 +183,17 @@ depo_status depo_seed(depo_ctx *ctx, const depo_sample_params *sp, const double 
  * (charges are rebuilt from the stored base charges).  Synchronises the stream. */
 depo_status depo_set_sample_params(depo_ctx *ctx, const depo_sample_params *sp, depo_stream stream);
 
-/* Advance all samples by n_steps >= 0 time steps.  Asynchronous: enqueues
- * the step sequence n_steps times on the stream (replaying a captured HIP
- * graph when possible) and returns without waiting. */
+/* Advance all samples by n_steps >= 0 time steps (Appendix A.2: drag half
+ * kick, drift, wall test, force evaluation, second half kick, tally).
+ * Asynchronous: enqueues the step n_steps times on the stream and returns
+ * without waiting.  With graphs enabled (the default) the step is captured
+ * once and replayed; with direct pair sums and short-range forces both on,
+ * the captured step runs the cell build and short-range forces beside the
+ * pair kernel (disjoint buffers, same kernels: results equal the direct
+ * launches bitwise).  Any call that changes the layout, the parameters, the
+ * pair mode or the state (seed, upload) drops the captured step.
+ * DEPO_E_STATE before depo_seed; DEPO_E_INVALID for n_steps < 0 or a step
+ * counter that would pass 2^31 - 1. */
 depo_status depo_step(depo_ctx *ctx, int32_t n_steps, depo_stream stream);
 
 /* Same as depo_step without graph replay, with HIP events recorded on the
