@@ -214,6 +214,22 @@ __device__ __forceinline__ int x_cell(uint64_t x, int n) { return (int)__umul64h
 __device__ __forceinline__ float sdiff(uint32_t a, uint32_t b) { return (float)(int32_t)(a - b); }
 __device__ __forceinline__ double sdiff(uint64_t a, uint64_t b) { return (double)(int64_t)(a - b); }
 
+// Centre displacement of particle i from particle j in metres (minimum image in x), its length,
+// and the surface gap |r| - s for the contact distance s = (d_i + d_j)/2, all in FP64 from the
+// exact integer differences of the fixed-point positions.  The gap is formed as
+// (|r|^2 - s^2) / (|r| + s): near contact it is a small fraction of |r|, and the plain
+// difference |r| - s would lose most of its digits.
+template <class Pos>
+__device__ __forceinline__ double pair_gap(Pos xi, Pos yi, Pos zi, Pos xj, Pos yj, Pos zj, double ux, double ur,
+                                           double s, double &dx, double &dy, double &dz, double &dist) {
+  dx = (double)as_signed(Pos(xi - xj)) * ux;
+  dy = (double)as_signed(Pos(yi - yj)) * ur;
+  dz = (double)as_signed(Pos(zi - zj)) * ur;
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  dist = sqrt(r2);
+  return (r2 - s * s) / (dist + s);
+}
+
 // Round a displacement in quanta to the nearest integer step.
 __device__ __forceinline__ int32_t round_step(float q) { return (int32_t)__builtin_rintf(q); }
 __device__ __forceinline__ int64_t round_step(double q) { return (int64_t)__builtin_rint(q); }

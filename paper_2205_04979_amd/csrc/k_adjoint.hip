@@ -385,10 +385,10 @@ __global__ __launch_bounds__(256) void k_short_range_vjp(State<Real> st, Phys ph
   const auto px = st.px[i], py = st.py[i], pz = st.pz[i];
   int cx, cy, cz, mx, my, mz;
   short_range_cells(px, py, pz, sp, cx, cy, cz, mx, my, mz);
-  const Real di = Real(st.d[i]);
+  const double di_d = st.d[i];
+  const Real di = Real(di_d);
   const Real mi = Real(ph.mass_coef) * di * di * di;
   const Real A = Real(sp.hamaker);
-  const Real ux = Real(ph.ux), ur = Real(ph.ur);
   const Real dsat = Real(ph.delta_sat);
   const bool vdw = (ph.flags & F_VDW) != 0, col = (ph.flags & F_COLLIDE) != 0;
   const Real wi[3] = {ad.ab[0][i] / mi, ad.ab[1][i] / mi, ad.ab[2][i] / mi};
@@ -413,15 +413,17 @@ __global__ __launch_bounds__(256) void k_short_range_vjp(State<Real> st, Phys ph
         for (int k = st.cell_start[c]; k < e; ++k) {
           const int j = st.cell_idx[k];
           if (j == i) continue;
-          const Real dx = sdiff(px, st.px[j]) * ux;
-          const Real dy = sdiff(py, st.py[j]) * ur;
-          const Real dz = sdiff(pz, st.pz[j]) * ur;
-          const Real dist = sqrt(dx * dx + dy * dy + dz * dz);
-          const Real dj = Real(st.d[j]);
-          const Real gap = dist - Real(0.5) * (di + dj);
-          if (gap > Real(0.25) * fmin(di, dj) || dist == Real(0)) continue;
-          const Real inv = Real(1) / dist;
-          const Real n[3] = {dx * inv, dy * inv, dz * inv};
+          // the forward's pair geometry and range test (FP64 gap)
+          const double dj_d = st.d[j];
+          double gx, gy, gz, gd;
+          const double gap_d = pair_gap(px, py, pz, st.px[j], st.py[j], st.pz[j], ph.ux, ph.ur,
+                                        0.5 * (di_d + dj_d), gx, gy, gz, gd);
+          if (gap_d > 0.25 * fmin(di_d, dj_d) || gd == 0.0) continue;
+          const double inv_d = 1.0 / gd;
+          const Real inv = Real(inv_d);
+          const Real n[3] = {Real(gx * inv_d), Real(gy * inv_d), Real(gz * inv_d)};
+          const Real dj = Real(dj_d);
+          const Real gap = Real(gap_d);
           const Real mj = Real(ph.mass_coef) * dj * dj * dj;
           // pair force on i along n: Fs = -F_vdw(gs) + [gap<0] m_eff (K overlap - H v_n)
           Real Fs = 0, Fr = 0, Fv = 0;

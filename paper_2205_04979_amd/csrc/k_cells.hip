@@ -145,10 +145,10 @@ __global__ __launch_bounds__(256) void k_short_range(State<Real> st, Phys ph, in
   const Real vix = st.vx[i], viy = st.vy[i], viz = st.vz[i];
   int cx, cy, cz, mx, my, mz;
   short_range_cells(px, py, pz, sp, cx, cy, cz, mx, my, mz);
-  const Real di = Real(st.d[i]);
+  const double di_d = st.d[i];
+  const Real di = Real(di_d);
   const Real mi = Real(ph.mass_coef) * di * di * di;
   const Real A = Real(sp.hamaker);
-  const Real ux = Real(ph.ux), ur = Real(ph.ur);
   const Real dsat = Real(ph.delta_sat);
   const bool vdw = (ph.flags & F_VDW) != 0, col = (ph.flags & F_COLLIDE) != 0;
   Real a0 = 0, a1 = 0, a2 = 0;
@@ -171,16 +171,17 @@ __global__ __launch_bounds__(256) void k_short_range(State<Real> st, Phys ph, in
         for (int k = st.cell_start[c]; k < e; ++k) {
           const int j = st.cell_idx[k];
           if (j == i) continue;
-          const Real dx = sdiff(px, st.px[j]) * ux;
-          const Real dy = sdiff(py, st.py[j]) * ur;
-          const Real dz = sdiff(pz, st.pz[j]) * ur;
-          const Real dist = sqrt(dx * dx + dy * dy + dz * dz);
-          const Real dj = Real(st.d[j]);
-          const Real gap = dist - Real(0.5) * (di + dj);
-          if (gap > Real(0.25) * fmin(di, dj) || dist == Real(0)) continue;
+          // geometry and the range test in FP64 (the gap near contact is a small fraction of |r|)
+          const double dj_d = st.d[j];
+          double gx, gy, gz, gd;
+          const double gap_d = pair_gap(px, py, pz, st.px[j], st.py[j], st.pz[j], ph.ux, ph.ur,
+                                        0.5 * (di_d + dj_d), gx, gy, gz, gd);
+          if (gap_d > 0.25 * fmin(di_d, dj_d) || gd == 0.0) continue;
           ++nb;
-          const Real inv = Real(1) / dist;
-          const Real nx = dx * inv, ny = dy * inv, nz = dz * inv;
+          const double inv_d = 1.0 / gd;
+          const Real nx = Real(gx * inv_d), ny = Real(gy * inv_d), nz = Real(gz * inv_d);
+          const Real dj = Real(dj_d);
+          const Real gap = Real(gap_d);
           Real f = 0;   // along +n (away from j), per unit mass of i
           if (vdw) f -= vdw_force(fmax(gap, dsat), di, dj, A) / mi;
           if (col && gap < Real(0)) {

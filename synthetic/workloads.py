@@ -14,6 +14,9 @@ Workloads (name: content):
 
 * ``plain-1k``: 1,024 particles, d = 10 um, q = +1e-15 C, A = 1e-20 J,
   64^3 field, Re_tau = 180, 200 steps.
+* ``plain-1k-dep``: ``plain-1k`` with dt = 3e-5 s (about 0.1 of the 10 um
+  particles' response time), so that the 200 steps span 6 ms and some twenty
+  particles reach the wall: the deposition tally has something to count.
 * ``single-65k``: 65,536 particles, d lognormal(ln 10 um, 0.3),
   q ~ N(0, (2e-15 C)^2), A = 5e-20 J, 128^3 field, all forces, 2,000 steps.
 * ``batched-256``: 256 Monte Carlo samples; per sample xi ~ U[0, 0.1],
@@ -135,6 +138,12 @@ def _plain_1k(n=1024, steps=200, field_n=64, seed=1, **kw):
     return Workload("plain-1k", p, field_n, 180, steps, np.array([0, n], np.int64), sp, x, d, qb)
 
 
+def _plain_1k_dep(dt=3e-5, **kw):
+    w = _plain_1k(dt=dt, **kw)
+    w.name = "plain-1k-dep"
+    return w
+
+
 def _single_65k(n=65536, steps=2000, field_n=128, seed=2, **kw):
     rng = np.random.default_rng(seed)
     p = physical_params(180.0, **kw)
@@ -201,6 +210,7 @@ def _rebound_theta_64(n_samples=64, n_per=16384, steps=1000, field_n=128, seed=6
 
 WORKLOADS = {
     "plain-1k": _plain_1k,
+    "plain-1k-dep": _plain_1k_dep,
     "single-65k": _single_65k,
     "batched-256": _batched_256,
     "adjoint-64x16k": _adjoint_64x16k,
