@@ -9,11 +9,12 @@ namespace depo {
 
 enum : int { ADJ_SEED = 1 };
 
-// One stored particle state: positions, velocity, non-drag acceleration, fluid
+// One stored particle state: positions (fixed point and remainder), velocity, non-drag acceleration, fluid
 // velocity and raw Coulomb sums (those that formed the acceleration), plus the
 // smoothed-tally accumulator when the entry is the final state.
 template <class Real> struct TapeEntry {
   typename Prec<Real>::Pos *px, *py, *pz;
+  Real *rx, *ry, *rz;
   Real *vx, *vy, *vz, *ax, *ay, *az, *ux, *uy, *uz, *cx, *cy, *cz;
   double *ell;
 };

@@ -87,6 +87,7 @@ template <class Real>
 struct State {
   using Pos = typename Prec<Real>::Pos;
   Pos *px, *py, *pz;
+  Real *rx, *ry, *rz;             // position remainder beyond the fixed-point value, in quanta (|r| <= 1/2)
   Real *vx, *vy, *vz;
   Real *ax, *ay, *az;             // stored non-drag acceleration a^n
   Real *ux, *uy, *uz;             // fluid velocity at the particle, u_f(x^n)
@@ -216,19 +217,24 @@ __device__ __forceinline__ double sdiff(uint64_t a, uint64_t b) { return (double
 
 // Centre displacement of particle i from particle j in metres (minimum image in x), its length,
 // and the surface gap |r| - s for the contact distance s = (d_i + d_j)/2, all in FP64 from the
-// exact integer differences of the fixed-point positions.  The gap is formed as
-// (|r|^2 - s^2) / (|r| + s): near contact it is a small fraction of |r|, and the plain
-// difference |r| - s would lose most of its digits.
+// exact integer differences of the fixed-point positions plus the difference of their
+// remainders (dr*, in quanta).  The gap is formed as (|r|^2 - s^2) / (|r| + s): near contact it
+// is a small fraction of |r|, and the plain difference |r| - s would lose most of its digits.
 template <class Pos>
-__device__ __forceinline__ double pair_gap(Pos xi, Pos yi, Pos zi, Pos xj, Pos yj, Pos zj, double ux, double ur,
-                                           double s, double &dx, double &dy, double &dz, double &dist) {
-  dx = (double)as_signed(Pos(xi - xj)) * ux;
-  dy = (double)as_signed(Pos(yi - yj)) * ur;
-  dz = (double)as_signed(Pos(zi - zj)) * ur;
+__device__ __forceinline__ double pair_gap(Pos xi, Pos yi, Pos zi, Pos xj, Pos yj, Pos zj, double drx, double dry,
+                                           double drz, double ux, double ur, double s, double &dx, double &dy,
+                                           double &dz, double &dist) {
+  dx = ((double)as_signed(Pos(xi - xj)) + drx) * ux;
+  dy = ((double)as_signed(Pos(yi - yj)) + dry) * ur;
+  dz = ((double)as_signed(Pos(zi - zj)) + drz) * ur;
   const double r2 = dx * dx + dy * dy + dz * dz;
   dist = sqrt(r2);
   return (r2 - s * s) / (dist + s);
 }
+
+// Position along y or z in metres: fixed-point value plus remainder.
+template <class Pos, class Real>
+__device__ __forceinline__ double pos_m(Pos p, Real r, double ur) { return ((double)as_signed(p) + (double)r) * ur; }
 
 // Round a displacement in quanta to the nearest integer step.
 __device__ __forceinline__ int32_t round_step(float q) { return (int32_t)__builtin_rintf(q); }

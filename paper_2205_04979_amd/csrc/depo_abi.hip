@@ -146,7 +146,7 @@ size_t carve(depo_ctx *ctx, char *base, State<Real> &st) {
   st.px = (Pos *)take(N * sizeof(Pos));
   st.py = (Pos *)take(N * sizeof(Pos));
   st.pz = (Pos *)take(N * sizeof(Pos));
-  Real **reals[] = {&st.vx, &st.vy, &st.vz, &st.ax, &st.ay, &st.az, &st.ux, &st.uy,
+  Real **reals[] = {&st.rx, &st.ry, &st.rz, &st.vx, &st.vy, &st.vz, &st.ax, &st.ay, &st.az, &st.ux, &st.uy,
                     &st.uz, &st.cx, &st.cy, &st.cz, &st.sx, &st.sy, &st.sz, &st.jr};
   for (Real **r : reals) *r = (Real *)take(N * sizeof(Real));
   st.d = (double *)take(N * sizeof(double));
@@ -547,6 +547,7 @@ depo_status do_seed(depo_ctx *ctx, const depo_sample_params *sp, const double *h
       return ctx->fail(DEPO_E_INVALID, "sample %d: parameters must be finite, hamaker >= 0", k);
   }
   std::vector<Pos> px(N), py(N), pz(N);
+  std::vector<Real> rx(N), ry(N), rz(N);   // remainders of the positions beyond the fixed-point values
   std::vector<int32_t> sid(N), zeros_i(N, 0);
   std::vector<double> zeros_d(N, 0.0);
   for (int k = 0; k < ctx->S; ++k)
@@ -564,12 +565,20 @@ depo_status do_seed(depo_ctx *ctx, const depo_sample_params *sp, const double *h
     const double sc = std::ldexp(fx, B);
     const double lim = std::ldexp(1.0, B);
     if constexpr (sizeof(Pos) == 4) {
-      px[i] = (Pos)(uint64_t)std::llround(sc >= lim ? 0.0 : sc);
+      const double k = std::nearbyint(sc);
+      rx[i] = (Real)(sc - k);
+      px[i] = (Pos)(uint64_t)(k >= lim ? 0.0 : k);
     } else {
+      // FP64 form: 2^-64 L quanta; the remainder is below the double's resolution of x
       px[i] = sc >= lim ? (Pos)0 : (Pos)sc;
+      rx[i] = 0;
     }
-    py[i] = (Pos)(SPos)std::llround(y * ctx->ph.inv_ur);
-    pz[i] = (Pos)(SPos)std::llround(z * ctx->ph.inv_ur);
+    const double qy = y * ctx->ph.inv_ur, qz = z * ctx->ph.inv_ur;
+    const double ky = std::nearbyint(qy), kz = std::nearbyint(qz);
+    py[i] = (Pos)(SPos)(int64_t)ky;
+    pz[i] = (Pos)(SPos)(int64_t)kz;
+    ry[i] = (Real)(qy - ky);
+    rz[i] = (Real)(qz - kz);
     if (hv) {
       for (int c = 0; c < 3; ++c)
         if (!std::isfinite(hv[3 * i + c]))
@@ -588,6 +597,9 @@ depo_status do_seed(depo_ctx *ctx, const depo_sample_params *sp, const double *h
   HIP_TRY(hipMemcpyAsync(st.px, px.data(), nb * sizeof(Pos), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(st.py, py.data(), nb * sizeof(Pos), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(st.pz, pz.data(), nb * sizeof(Pos), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(st.rx, rx.data(), nb * sizeof(Real), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(st.ry, ry.data(), nb * sizeof(Real), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(st.rz, rz.data(), nb * sizeof(Real), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(st.d, hd, nb * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(st.qb, hq, nb * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(st.ell, zeros_d.data(), nb * 8, hipMemcpyHostToDevice, s));
@@ -659,18 +671,25 @@ depo_status do_read(depo_ctx *ctx, double *hx, double *hv, double *ha, int32_t *
   const size_t N = (size_t)ctx->N;
   if (hx) {
     std::vector<Pos> p(3 * N);
+    std::vector<Real> r(3 * N);
     HIP_TRY(hipMemcpyAsync(p.data(), st.px, N * sizeof(Pos), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(p.data() + N, st.py, N * sizeof(Pos), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(p.data() + 2 * N, st.pz, N * sizeof(Pos), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(r.data(), st.rx, N * sizeof(Real), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(r.data() + N, st.ry, N * sizeof(Real), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(r.data() + 2 * N, st.rz, N * sizeof(Real), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     for (size_t i = 0; i < N; ++i) {
-      hx[3 * i] = (double)p[i] * ctx->ph.ux;
+      double x = ((double)p[i] + (double)r[i]) * ctx->ph.ux;
+      if (x < 0.0) x += ctx->p.L;
+      if (x >= ctx->p.L) x -= ctx->p.L;
+      hx[3 * i] = x;
       if constexpr (sizeof(Pos) == 4) {
-        hx[3 * i + 1] = (double)(int32_t)p[N + i] * ctx->ph.ur;
-        hx[3 * i + 2] = (double)(int32_t)p[2 * N + i] * ctx->ph.ur;
+        hx[3 * i + 1] = ((double)(int32_t)p[N + i] + (double)r[N + i]) * ctx->ph.ur;
+        hx[3 * i + 2] = ((double)(int32_t)p[2 * N + i] + (double)r[2 * N + i]) * ctx->ph.ur;
       } else {
-        hx[3 * i + 1] = (double)(int64_t)p[N + i] * ctx->ph.ur;
-        hx[3 * i + 2] = (double)(int64_t)p[2 * N + i] * ctx->ph.ur;
+        hx[3 * i + 1] = ((double)(int64_t)p[N + i] + (double)r[N + i]) * ctx->ph.ur;
+        hx[3 * i + 2] = ((double)(int64_t)p[2 * N + i] + (double)r[2 * N + i]) * ctx->ph.ur;
       }
     }
   }
@@ -719,11 +738,12 @@ template <class Real> depo_status do_tally(depo_ctx *ctx, depo_tally *out, hipSt
   return check_err<Real>(ctx, s);
 }
 
-// checkpoint payload: positions, velocities, accelerations, fluid velocities,
-// d, qbase, ell, dep, per-sample parameters
+// checkpoint payload: positions (fixed point, then remainders), velocities, accelerations,
+// fluid velocities, d, qbase, ell, dep, per-sample parameters
+constexpr uint32_t kBlobVersion = 2;
 template <class Real> size_t blob_payload(const depo_ctx *ctx) {
   const size_t N = (size_t)ctx->N;
-  return N * (3 * sizeof(typename Prec<Real>::Pos) + 9 * sizeof(Real) + 3 * 8 + 4) +
+  return N * (3 * sizeof(typename Prec<Real>::Pos) + 12 * sizeof(Real) + 3 * 8 + 4) +
          (size_t)ctx->S * sizeof(depo_sample_params);
 }
 
@@ -742,7 +762,7 @@ template <class Real> depo_status do_download(depo_ctx *ctx, void *blob, size_t 
   depo_status r;
   for (const Pos *a : {st.px, st.py, st.pz})
     if ((r = get(a, N * sizeof(Pos))) != DEPO_OK) return r;
-  for (const Real *a : {st.vx, st.vy, st.vz, st.ax, st.ay, st.az, st.ux, st.uy, st.uz})
+  for (const Real *a : {st.rx, st.ry, st.rz, st.vx, st.vy, st.vz, st.ax, st.ay, st.az, st.ux, st.uy, st.uz})
     if ((r = get(a, N * sizeof(Real))) != DEPO_OK) return r;
   for (const double *a : {st.d, st.qb, st.ell})
     if ((r = get(a, N * 8)) != DEPO_OK) return r;
@@ -751,7 +771,7 @@ template <class Real> depo_status do_download(depo_ctx *ctx, void *blob, size_t 
   std::memcpy(p, ctx->sp.data(), ctx->S * sizeof(depo_sample_params));
   BlobHeader h{};
   std::memcpy(h.magic, "DEPOCKPT", 8);
-  h.version = 1;
+  h.version = kBlobVersion;
   h.real_bytes = (uint32_t)ctx->p.real_bytes;
   h.n = ctx->N;
   h.s = ctx->S;
@@ -770,13 +790,13 @@ template <class Real> depo_status do_upload(depo_ctx *ctx, const void *blob, siz
   if (bytes != sizeof(BlobHeader) + pay) return ctx->fail(DEPO_E_CORRUPT, "blob size mismatch");
   BlobHeader h;
   std::memcpy(&h, blob, sizeof h);
-  if (std::memcmp(h.magic, "DEPOCKPT", 8) != 0 || h.version != 1 || h.real_bytes != (uint32_t)ctx->p.real_bytes ||
+  if (std::memcmp(h.magic, "DEPOCKPT", 8) != 0 || h.version != kBlobVersion || h.real_bytes != (uint32_t)ctx->p.real_bytes ||
       h.n != ctx->N || h.s != ctx->S || h.payload != pay || h.nstep < 0)
     return ctx->fail(DEPO_E_CORRUPT, "blob header does not match this context");
   const char *p = (const char *)blob + sizeof(BlobHeader);
   if (crc32_update(0, p, pay) != h.crc) return ctx->fail(DEPO_E_CORRUPT, "blob CRC mismatch");
   // per-sample parameters and diameters rebuild the sample table
-  const char *q = p + N * (3 * sizeof(Pos) + 9 * sizeof(Real));
+  const char *q = p + N * (3 * sizeof(Pos) + 12 * sizeof(Real));
   std::vector<double> d(N);
   std::memcpy(d.data(), q, N * 8);
   std::vector<depo_sample_params> sp(ctx->S);
@@ -803,7 +823,7 @@ template <class Real> depo_status do_upload(depo_ctx *ctx, const void *blob, siz
   };
   for (Pos *a : {st.px, st.py, st.pz})
     if ((r = put(a, N * sizeof(Pos))) != DEPO_OK) return r;
-  for (Real *a : {st.vx, st.vy, st.vz, st.ax, st.ay, st.az, st.ux, st.uy, st.uz})
+  for (Real *a : {st.rx, st.ry, st.rz, st.vx, st.vy, st.vz, st.ax, st.ay, st.az, st.ux, st.uy, st.uz})
     if ((r = put(a, N * sizeof(Real))) != DEPO_OK) return r;
   for (double *a : {st.d, st.qb, st.ell})
     if ((r = put(a, N * 8)) != DEPO_OK) return r;
@@ -848,7 +868,7 @@ size_t carve_adjoint(const depo_ctx *ctx, char *base, int n_steps, int n_ckpt, i
   auto entry = [&](bool ell) {
     TapeEntry<Real> t{};
     t.px = (Pos *)take(N * sizeof(Pos)); t.py = (Pos *)take(N * sizeof(Pos)); t.pz = (Pos *)take(N * sizeof(Pos));
-    Real **r[] = {&t.vx, &t.vy, &t.vz, &t.ax, &t.ay, &t.az, &t.ux, &t.uy, &t.uz, &t.cx, &t.cy, &t.cz};
+    Real **r[] = {&t.rx, &t.ry, &t.rz, &t.vx, &t.vy, &t.vz, &t.ax, &t.ay, &t.az, &t.ux, &t.uy, &t.uz, &t.cx, &t.cy, &t.cz};
     for (Real **q : r) *q = (Real *)take(N * sizeof(Real));
     t.ell = ell ? (double *)take(N * 8) : nullptr;
     return t;

@@ -29,6 +29,7 @@ __global__ __launch_bounds__(256) void k_tape_store(State<Real> st, TapeEntry<Re
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   t.px[i] = st.px[i]; t.py[i] = st.py[i]; t.pz[i] = st.pz[i];
+  t.rx[i] = st.rx[i]; t.ry[i] = st.ry[i]; t.rz[i] = st.rz[i];
   t.vx[i] = st.vx[i]; t.vy[i] = st.vy[i]; t.vz[i] = st.vz[i];
   t.ax[i] = st.ax[i]; t.ay[i] = st.ay[i]; t.az[i] = st.az[i];
   t.ux[i] = st.ux[i]; t.uy[i] = st.uy[i]; t.uz[i] = st.uz[i];
@@ -41,6 +42,7 @@ __global__ __launch_bounds__(256) void k_tape_load(State<Real> st, TapeEntry<Rea
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   st.px[i] = t.px[i]; st.py[i] = t.py[i]; st.pz[i] = t.pz[i];
+  st.rx[i] = t.rx[i]; st.ry[i] = t.ry[i]; st.rz[i] = t.rz[i];
   st.vx[i] = t.vx[i]; st.vy[i] = t.vy[i]; st.vz[i] = t.vz[i];
   st.ax[i] = t.ax[i]; st.ay[i] = t.ay[i]; st.az[i] = t.az[i];
   st.ux[i] = t.ux[i]; st.uy[i] = t.uy[i]; st.uz[i] = t.uz[i];
@@ -181,7 +183,7 @@ __global__ __launch_bounds__(256) void k_adj_post(State<Real> st, Phys ph, TapeE
   Real xb[3] = {0, 0, 0}, vpb[3] = {0, 0, 0};
   Real ab[3] = {ad.ab[0][i], ad.ab[1][i], ad.ab[2][i]};
   Real ub[3] = {ad.ub[0][i], ad.ub[1][i], ad.ub[2][i]};
-  const double y = (double)as_signed(py) * ph.ur, z = (double)as_signed(pz) * ph.ur;
+  const double y = pos_m(py, s1.ry[i], ph.ur), z = pos_m(pz, s1.rz[i], ph.ur);
   const double rho = sqrt(y * y + z * z);
   const double ery = rho > 0.0 ? y / rho : 0.0, erz = rho > 0.0 ? z / rho : 0.0;
 
@@ -256,8 +258,8 @@ __global__ __launch_bounds__(256) void k_adj_post(State<Real> st, Phys ph, TapeE
     // source record of the pair adjoint: b = c a_bar with c = k_e q q_ref / (m ux^2)
     JAdj<Real> r;
     r.x = px;
-    r.y = Real((double)as_signed(py) * ph.yz_over_x);
-    r.z = Real((double)as_signed(pz) * ph.yz_over_x);
+    r.y = Real(y * ph.inv_ux);
+    r.z = Real(z * ph.inv_ux);
     r.q = Real(q / ph.q_ref);
     const double c = ph.k_e * q * ph.q_ref / (m * ph.ux * ph.ux);
     r.bx = Real(c * ab[0]); r.by = Real(c * ab[1]); r.bz = Real(c * ab[2]);
@@ -383,6 +385,7 @@ __global__ __launch_bounds__(256) void k_short_range_vjp(State<Real> st, Phys ph
   const int i = st.cell_idx[t];
   const SampleDev sp = st.samples[st.sid[i]];
   const auto px = st.px[i], py = st.py[i], pz = st.pz[i];
+  const double rxi = st.rx[i], ryi = st.ry[i], rzi = st.rz[i];
   int cx, cy, cz, mx, my, mz;
   short_range_cells(px, py, pz, sp, cx, cy, cz, mx, my, mz);
   const double di_d = st.d[i];
@@ -416,7 +419,8 @@ __global__ __launch_bounds__(256) void k_short_range_vjp(State<Real> st, Phys ph
           // the forward's pair geometry and range test (FP64 gap)
           const double dj_d = st.d[j];
           double gx, gy, gz, gd;
-          const double gap_d = pair_gap(px, py, pz, st.px[j], st.py[j], st.pz[j], ph.ux, ph.ur,
+          const double gap_d = pair_gap(px, py, pz, st.px[j], st.py[j], st.pz[j], rxi - (double)st.rx[j],
+                                        ryi - (double)st.ry[j], rzi - (double)st.rz[j], ph.ux, ph.ur,
                                         0.5 * (di_d + dj_d), gx, gy, gz, gd);
           if (gap_d > 0.25 * fmin(di_d, dj_d) || gd == 0.0) continue;
           const double inv_d = 1.0 / gd;

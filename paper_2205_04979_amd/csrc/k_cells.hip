@@ -142,6 +142,7 @@ __global__ __launch_bounds__(256) void k_short_range(State<Real> st, Phys ph, in
   const int i = st.cell_idx[t];
   const SampleDev sp = st.samples[st.sid[i]];
   const auto px = st.px[i], py = st.py[i], pz = st.pz[i];
+  const double rxi = st.rx[i], ryi = st.ry[i], rzi = st.rz[i];
   const Real vix = st.vx[i], viy = st.vy[i], viz = st.vz[i];
   int cx, cy, cz, mx, my, mz;
   short_range_cells(px, py, pz, sp, cx, cy, cz, mx, my, mz);
@@ -174,7 +175,8 @@ __global__ __launch_bounds__(256) void k_short_range(State<Real> st, Phys ph, in
           // geometry and the range test in FP64 (the gap near contact is a small fraction of |r|)
           const double dj_d = st.d[j];
           double gx, gy, gz, gd;
-          const double gap_d = pair_gap(px, py, pz, st.px[j], st.py[j], st.pz[j], ph.ux, ph.ur,
+          const double gap_d = pair_gap(px, py, pz, st.px[j], st.py[j], st.pz[j], rxi - (double)st.rx[j],
+                                        ryi - (double)st.ry[j], rzi - (double)st.rz[j], ph.ux, ph.ur,
                                         0.5 * (di_d + dj_d), gx, gy, gz, gd);
           if (gap_d > 0.25 * fmin(di_d, dj_d) || gd == 0.0) continue;
           ++nb;

@@ -54,11 +54,12 @@ template <class Real>
 __device__ __forceinline__ void mesh_coords(const State<Real> &st, const Phys &ph, const P3mDev &m, int i, double &gx,
                                             double &gy, double &gz) {
   using SPos = typename std::make_signed<typename Prec<Real>::Pos>::type;
-  const double x = (double)st.px[i] * ph.ux;
-  const double y = (double)(SPos)st.py[i] * ph.ur;
-  const double z = (double)(SPos)st.pz[i] * ph.ur;
+  const double x = ((double)st.px[i] + (double)st.rx[i]) * ph.ux;
+  const double y = ((double)(SPos)st.py[i] + (double)st.ry[i]) * ph.ur;
+  const double z = ((double)(SPos)st.pz[i] + (double)st.rz[i]) * ph.ur;
   gx = x / m.hx;
   if (gx >= m.nx) gx -= m.nx;
+  if (gx < 0.0) gx += m.nx;
   gy = (y + ph.R) / m.hy + 1.0;
   gz = (z + ph.R) / m.hy + 1.0;
 }
@@ -398,9 +399,9 @@ __global__ void k_p3m_interp(State<Real> st, Phys ph, P3mDev m, const int32_t *_
 template <class Real>
 __device__ __forceinline__ int3 sr_cell(const State<Real> &st, const Phys &ph, const P3mDev &m, int i) {
   using SPos = typename std::make_signed<typename Prec<Real>::Pos>::type;
-  const double x = (double)st.px[i] * ph.ux;
-  const double y = (double)(SPos)st.py[i] * ph.ur;
-  const double z = (double)(SPos)st.pz[i] * ph.ur;
+  const double x = ((double)st.px[i] + (double)st.rx[i]) * ph.ux;
+  const double y = ((double)(SPos)st.py[i] + (double)st.ry[i]) * ph.ur;
+  const double z = ((double)(SPos)st.pz[i] + (double)st.rz[i]) * ph.ur;
   int cx = (int)(x / ph.L * m.ncx), cy = (int)((y + ph.R) / (2.0 * ph.R) * m.ncy),
       cz = (int)((z + ph.R) / (2.0 * ph.R) * m.ncy);
   cx = min(max(cx, 0), m.ncx - 1);
@@ -419,9 +420,9 @@ __global__ void k_p3m_bin(State<Real> st, Phys ph, P3mDev m, int32_t *__restrict
   if (i >= ph.N) return;
   const int3 c = sr_cell<Real>(st, ph, m, i);
   const int id = (c.x * m.ncy + c.y) * m.ncy + c.z;
-  const double x = (double)st.px[i] * ph.ux;
-  const double y = (double)(SPos)st.py[i] * ph.ur;
-  const double z = (double)(SPos)st.pz[i] * ph.ur;
+  const double x = ((double)st.px[i] + (double)st.rx[i]) * ph.ux;
+  const double y = ((double)(SPos)st.py[i] + (double)st.ry[i]) * ph.ur;
+  const double z = ((double)(SPos)st.pz[i] + (double)st.rz[i]) * ph.ur;
   const int hx = (x / ph.L * m.ncx - c.x) >= 0.5, hy = ((y + ph.R) / (2.0 * ph.R) * m.ncy - c.y) >= 0.5,
             hz = ((z + ph.R) / (2.0 * ph.R) * m.ncy - c.z) >= 0.5;
   cell_of[i] = 8 * id + 4 * hx + 2 * hy + hz;
@@ -519,8 +520,8 @@ __global__ void k_p3m_records(State<Real> st, Phys ph, const int32_t *__restrict
     // FP32 form: y and z as floats in y/z position quanta (bit patterns in the Pos fields), so that
     // the short-range body takes their differences with one subtraction
     using SPos = typename std::make_signed<typename Prec<Real>::Pos>::type;
-    r.y = __float_as_uint((float)(SPos)st.py[i]);
-    r.z = __float_as_uint((float)(SPos)st.pz[i]);
+    r.y = __float_as_uint((float)((double)(SPos)st.py[i] + (double)st.ry[i]));
+    r.z = __float_as_uint((float)((double)(SPos)st.pz[i] + (double)st.rz[i]));
   } else {
     r.y = st.py[i];
     r.z = st.pz[i];

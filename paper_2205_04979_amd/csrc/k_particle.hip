@@ -69,6 +69,7 @@ __global__ __launch_bounds__(256) void k_prepare(State<Real> st, Phys ph, int mo
   const int step = *st.nstep + 1;
   bool alive = st.dep[i] == 0;
   Pos px = st.px[i], py = st.py[i], pz = st.pz[i];
+  Real rx = st.rx[i], ry = st.ry[i], rz = st.rz[i];
   const double d = st.d[i];
   const int s = st.sid[i];
   if (mode & P_SEED) st.jr[i] = Real(0.5 * d * ph.inv_ux);
@@ -82,11 +83,19 @@ __global__ __launch_bounds__(256) void k_prepare(State<Real> st, Phys ph, int mo
     const Real qx = Real(ph.dt * ph.inv_ux), qr = Real(ph.dt * ph.inv_ur);
     // keep one step's displacement inside the signed range of the fixed-point type
     const Real lim = sizeof(Real) == 4 ? Real(1 << 30) : Real(0x1p62);
-    px += (Pos)round_step(fmin(fmax(v[0] * qx, -lim), lim));
-    py = (Pos)(as_signed(py) + round_step(fmin(fmax(v[1] * qr, -lim), lim)));
-    pz = (Pos)(as_signed(pz) + round_step(fmin(fmax(v[2] * qr, -lim), lim)));
+    // compensated drift: the displacement in quanta plus the carried remainder is split into the
+    // integer step added to the fixed-point position and the new remainder (exact: q - rint(q)),
+    // so rounding to the quantum does not accumulate from step to step
+    const Real mx = fmin(fmax(fma(v[0], qx, rx), -lim), lim);
+    const Real my = fmin(fmax(fma(v[1], qr, ry), -lim), lim);
+    const Real mz = fmin(fmax(fma(v[2], qr, rz), -lim), lim);
+    const auto kx = round_step(mx), ky = round_step(my), kz = round_step(mz);
+    rx = mx - Real(kx); ry = my - Real(ky); rz = mz - Real(kz);
+    px += (Pos)kx;
+    py = (Pos)(as_signed(py) + ky);
+    pz = (Pos)(as_signed(pz) + kz);
     if (!(ph.flags & F_SOFT)) {
-      const double y = (double)as_signed(py) * ph.ur, z = (double)as_signed(pz) * ph.ur;
+      const double y = pos_m(py, ry, ph.ur), z = pos_m(pz, rz, ph.ur);
       const double rho = sqrt(y * y + z * z);
       if (rho + 0.5 * d >= ph.R) {
         bool stick = true;
@@ -108,8 +117,12 @@ __global__ __launch_bounds__(256) void k_prepare(State<Real> st, Phys ph, int mo
             v[2] = Real((double)v[2] - dv * erz);
             const double pen = rho + 0.5 * d - ph.R;
             const double sc = (rho - 2.0 * pen) / rho;
-            py = (Pos)round_step(y * sc * ph.inv_ur);
-            pz = (Pos)round_step(z * sc * ph.inv_ur);
+            const double ny = y * sc * ph.inv_ur, nz = z * sc * ph.inv_ur;
+            const auto jy = round_step(ny), jz = round_step(nz);
+            py = (Pos)jy;
+            pz = (Pos)jz;
+            ry = Real(ny - (double)jy);
+            rz = Real(nz - (double)jz);
           }
         }
         if (stick) {
@@ -121,12 +134,13 @@ __global__ __launch_bounds__(256) void k_prepare(State<Real> st, Phys ph, int mo
     }
     st.vx[i] = v[0]; st.vy[i] = v[1]; st.vz[i] = v[2];
     st.px[i] = px; st.py[i] = py; st.pz[i] = pz;
+    st.rx[i] = rx; st.ry[i] = ry; st.rz[i] = rz;
   }
   if (mode & P_COULOMB) {
     JSrc<Real> js;
     js.x = px;
-    js.y = Real((double)as_signed(py) * ph.yz_over_x);
-    js.z = Real((double)as_signed(pz) * ph.yz_over_x);
+    js.y = Real(((double)as_signed(py) + (double)ry) * ph.yz_over_x);
+    js.z = Real(((double)as_signed(pz) + (double)rz) * ph.yz_over_x);
     js.q = alive ? Real(st.samples[s].charge_scale * st.qb[i] / ph.q_ref) : Real(0);
     st.js[i] = js;
   }
@@ -179,8 +193,8 @@ __global__ __launch_bounds__(256) void k_finish(State<Real> st, Phys ph, int mod
     a[0] += st.sx[i]; a[1] += st.sy[i]; a[2] += st.sz[i];
   }
   const auto py = st.py[i], pz = st.pz[i];
+  const double y = pos_m(py, st.ry[i], ph.ur), z = pos_m(pz, st.rz[i], ph.ur);
   if (ph.flags & (F_WALL_IMAGE | F_WALL_VDW)) {
-    const double y = (double)as_signed(py) * ph.ur, z = (double)as_signed(pz) * ph.ur;
     const double rho = sqrt(y * y + z * z);
     if (rho > 0.0) {
       const double h = fmax(ph.R - rho, 0.5 * d);    // centre-to-wall distance, never below contact
@@ -212,7 +226,6 @@ __global__ __launch_bounds__(256) void k_finish(State<Real> st, Phys ph, int mod
     half_kick(v, u, a, Real(d), Real(ph.tau_coef * d * d), Real(0.5 * ph.dt), Real(1.0 / ph.nu),
               (ph.flags & F_DRAG) != 0);
     if (ph.flags & F_SOFT) {
-      const double y = (double)as_signed(py) * ph.ur, z = (double)as_signed(pz) * ph.ur;
       const double g = ph.R - sqrt(y * y + z * z) - 0.5 * d;
       const double zz = -g / (ph.soft_eps * d);
       st.ell[i] += ph.soft_rate * ph.dt / (1.0 + exp(-zz));

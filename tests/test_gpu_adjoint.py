@@ -168,6 +168,45 @@ def test_fp64_adjoint_matches_gpu_finite_differences_and_is_checkpoint_invariant
         assert np.allclose(grads[0][:, c], fds[0], rtol=1e-3, atol=0), (c, grads[0][:, c], fds[0])
 
 
+def snap_to_fp32_lattice(x, p):
+    """Positions rounded to the FP32 form's fixed-point lattice (x to L/2^32, y and z to R/2^30), which
+    the FP64 form holds exactly: both forms then start from the same positions."""
+    ux, ur = p["L"] / 2.0 ** 32, p["R"] / 2.0 ** 30
+    y = np.array(x, dtype=np.float64)
+    y[:, 0] = np.round(np.mod(y[:, 0], p["L"]) / ux) * ux
+    y[:, 1:] = np.round(y[:, 1:] / ur) * ur
+    return y
+
+
+@pytest.mark.parametrize("name", ["drag+image", "coulomb", "contact+pair-vdw", "drag+wall-vdw", "all"])
+def test_fp32_adjoint_per_force_family(name):
+    """Each force family alone, and all together, from the same start in both forms (positions on the FP32
+    lattice): the FP32 adjoint against the FP64 adjoint per entry after one step (the reverse kernels'
+    own arithmetic) and after 16 steps (plus the FP32 trajectory's departure from the FP64 one), within
+    1e-5.  The Coulomb family's bound is 5e-4: its pairs sit within a diameter of each other next to the
+    wall, where the FP32 pair records hold y and z to 64 position quanta (relative 6e-5 of a 10 um
+    separation, about 3x that in the Jacobian of the pair force)."""
+    fam = FORCE_SETS.get(name, {})
+    tol = 5e-4 if name == "coulomb" else 1e-5
+    say("case: fp32 vs fp64 adjoint, family", name)
+    for n in (1, 16):
+        p, f, x, d, q, off, sp, v0 = sensitive_case(seed=17)
+        p.update(fam)
+        x = snap_to_fp32_lattice(x, p)
+        g = {}
+        for rb in (8, 4):
+            sim = gpu_sim(p, f, off, rb)
+            sim.seed(sp, x, d, q, v=v0)
+            g[rb] = sim.adjoint(n, min(n, 5))
+        ref = g[8][:, :2]
+        used = np.abs(ref) > 0
+        rel = np.abs(g[4][:, :2] - ref)[used] / np.abs(ref)[used]
+        say(name, "steps", n, "fp64", ref.tolist(), "largest relative deviation per entry", rel.max())
+        assert used.sum() >= 2
+        assert np.all(g[4][:, :2][~used] == 0.0)
+        assert rel.max() < tol, (name, n, rel)
+
+
 def test_fp32_adjoint_close_to_fp64_adjoint():
     p, f, x, d, q, off, sp, v0 = sensitive_case(seed=10)
     n, ce = 20, 10
@@ -178,7 +217,7 @@ def test_fp32_adjoint_close_to_fp64_adjoint():
         sim.seed(sp, x, d, q, v=v0)
         g[rb] = sim.adjoint(n, ce)
     say("fp64", g[8][:, :2].tolist(), "fp32", g[4][:, :2].tolist())
-    assert np.allclose(g[4][:, :2], g[8][:, :2], rtol=2e-3, atol=0)
+    assert np.allclose(g[4][:, :2], g[8][:, :2], rtol=5e-4, atol=0)
 
 
 @pytest.mark.parametrize("shape", [(4, 1), (2, 2), (4, 2), (8, 1)])
@@ -205,7 +244,7 @@ def test_fp32_symmetric_pair_adjoint_matches_one_sided(shape):
     assert np.all(np.abs(g["fp64"]) > 0)
     assert np.allclose(g["sym"], g["sym2"], rtol=1e-12, atol=0)
     assert np.allclose(g["sym"], g["one"], rtol=5e-4, atol=0)
-    assert np.allclose(g["sym"], g["fp64"], rtol=2e-3, atol=0)
+    assert np.allclose(g["sym"], g["fp64"], rtol=5e-4, atol=0)
 
 
 def test_autograd_function_backward():
@@ -274,8 +313,10 @@ def test_adjoint_64x16k_full_size():
     checkpoints every 10).  FP32 with the symmetric pair adjoint (the benchmark's configuration): its own
     forward run gives bitwise the J of a plain forward run, and its gradient agrees with the one-sided FP32
     pair adjoint and with the FP64 adjoint.  FP64: the adjoint agrees with central differences of the
-    library's FP64 forward run, for all samples at once (a sample's J depends only on its own parameters).
-    Tolerances are relative to the largest entry of each gradient column."""
+    library's FP64 forward run, for all samples at once (a sample's J depends only on its own parameters),
+    on the samples whose J is smooth over the difference interval.  Every comparison is per entry
+    (relative to the FP64 adjoint's entry) over the entries larger than 1e-3 of their column's largest,
+    held to 1e-3."""
     from paper_2205_04979_amd.depo import PAIR_KAHAN, PAIR_SYMMETRIC
     w = make_workload("adjoint-64x16k")
     f = w.field()
@@ -302,19 +343,29 @@ def test_adjoint_64x16k_full_size():
             assert np.array_equal(j_fwd, np.array([t["j_soft"] for t in sim.tally()])), key
         say(key, "gradient of sample 0", g[key][0].tolist())
         if key == "fp64":
-            fd = np.zeros((w.n_samples, 2))
+            fd = np.zeros((2, w.n_samples, 2))
             for c in range(2):
-                hp, hm = sp.copy(), sp.copy()
-                hp[:, c] *= 1 + H_REL
-                hm[:, c] *= 1 - H_REL
-                fd[:, c] = (J(sim, hp) - J(sim, hm)) / (2 * H_REL * sp[:, c])
+                for k, h in enumerate((H_REL, 3 * H_REL)):
+                    hp, hm = sp.copy(), sp.copy()
+                    hp[:, c] *= 1 + h
+                    hm[:, c] *= 1 - h
+                    fd[k, :, c] = (J(sim, hp) - J(sim, hm)) / (2 * h * sp[:, c])
         del sim
     for c in range(2):
-        scale = np.abs(g["fp64"][:, c]).max()
+        ref = g["fp64"][:, c]
+        scale = np.abs(ref).max()
         assert scale > 0
-        dev = {k: np.abs(v[:, c] - g["fp64"][:, c]).max() / scale for k, v in g.items() if k != "fp64"}
-        dev["fd"] = np.abs(fd[:, c] - g["fp64"][:, c]).max() / scale
-        dev["sym-one"] = np.abs(g["sym"][:, c] - g["one"][:, c]).max() / scale
-        say("column", c, "deviation / max |grad|", dev)
-        assert dev["fd"] < 1e-3 and dev["sym"] < 2e-3 and dev["one"] < 2e-3 and dev["sym-one"] < 5e-4, (c, dev)
+        # per entry, wherever the gradient is not negligible against the column's largest entry
+        big = np.abs(ref) > 1e-3 * scale
+        dev = {k: (np.abs(v[:, c] - ref) / np.abs(ref))[big].max() for k, v in g.items() if k != "fp64"}
+        dev["sym-one"] = (np.abs(g["sym"][:, c] - g["one"][:, c]) / np.abs(ref))[big].max()
+        # finite differences measure the derivative only where J is smooth over the +-3h interval (a
+        # cohesion cutoff crossing inside it is a jump): such samples show as disagreeing h and 3h
+        # differences and are left out of the FD comparison, and counted
+        smooth = big & (np.abs(fd[0, :, c] - fd[1, :, c]) <= 2e-4 * np.abs(fd[0, :, c]))
+        dev["fd"] = (np.abs(fd[0, :, c] - ref) / np.abs(ref))[smooth].max()
+        say("column", c, "entries", int(big.sum()), "smooth over +-3h", int(smooth.sum()),
+            "largest relative deviation per entry", dev)
+        assert big.sum() >= 32 and smooth.sum() >= 0.75 * big.sum()
+        assert dev["fd"] < 1e-3 and dev["sym"] < 1e-3 and dev["one"] < 1e-3 and dev["sym-one"] < 5e-4, (c, dev)
     assert np.all(g["sym"][:, 2] == 0) and np.all(g["fp64"][:, 2] == 0)
