@@ -210,7 +210,12 @@ enum {
   DEPO_PAIR_SYMMETRIC = 2,  /* FP32 only: every unordered pair once, the reaction applied to
                              * the source (Newton's third law); Kahan on the target side,
                              * 64-bit fixed-point combination of per-item partials          */
-  DEPO_PAIR_P3M = 3         /* P3M electrostatics (configured with depo_set_p3m)           */
+  DEPO_PAIR_P3M = 3,        /* P3M electrostatics (configured with depo_set_p3m)           */
+  DEPO_PAIR_SYMMETRIC_INT = 4 /* FP32 only: DEPO_PAIR_SYMMETRIC with the y and z coordinates of
+                             * the source records held as 32-bit integers in x quanta
+                             * (L/2^32) instead of floats, so that every coordinate difference
+                             * of a pair is exact (the float records hold y and z to 64 quanta
+                             * near the wall); needs L >= 2R; about 10 % slower           */
 };
 
 /* Choose the Coulomb pair-kernel shape (targets per lane, wavefronts per

@@ -29,7 +29,9 @@ template <> struct Prec<double> {
 
 // Coulomb source record streamed through the scalar cache by the pair kernel:
 // raw x bits, y and z in units of the x quantum, and the scaled charge (0 for
-// a removed particle, so it drops out of every sum without compaction).
+// a removed particle, so it drops out of every sum without compaction).  With
+// F_INT_RECORDS (FP32) y and z are rounded to integers in x quanta and stored as
+// int32 bit patterns, so that every coordinate difference of a pair is exact.
 template <class Real> struct JSrc;
 template <> struct __align__(16) JSrc<float> { uint32_t x; float y, z, q; };
 template <> struct __align__(32) JSrc<double> { uint64_t x; double y, z, q; };
@@ -80,6 +82,10 @@ enum : uint32_t {
   F_DRAG = 1u << 0, F_COULOMB = 1u << 1, F_COLLIDE = 1u << 2, F_VDW = 1u << 3, F_VDW_GU = 1u << 4,
   F_WALL_IMAGE = 1u << 5, F_WALL_VDW = 1u << 6, F_REBOUND = 1u << 7, F_SOFT = 1u << 8, F_BODY = 1u << 9
 };
+
+// Internal switch (not a depo_params flag): the Coulomb source records hold y and z as 32-bit
+// integers in x quanta (bit patterns in the float fields) for the symmetric integer-record kernel.
+enum : uint32_t { F_INT_RECORDS = 1u << 16 };
 
 enum : uint32_t { ERR_NONFINITE = 1u };
 

@@ -199,6 +199,12 @@ template <class Real> State<Real> &state(depo_ctx *ctx);
 template <> State<float> &state<float>(depo_ctx *ctx) { return ctx->sf; }
 template <> State<double> &state<double>(depo_ctx *ctx) { return ctx->sd; }
 
+// The Coulomb source records hold integer y and z only for the symmetric integer-record kernel.
+void set_record_format(depo_ctx *ctx) {
+  ctx->ph.flags &= ~F_INT_RECORDS;
+  if (ctx->ccfg.int_rec && !ctx->fp64()) ctx->ph.flags |= F_INT_RECORDS;
+}
+
 void fill_phys(depo_ctx *ctx) {
   const depo_params &p = ctx->p;
   Phys &ph = ctx->ph;
@@ -235,6 +241,7 @@ void fill_phys(depo_ctx *ctx) {
   ph.nx = ctx->nx;
   ph.ny = ctx->ny;
   ph.nz = ctx->nz;
+  set_record_format(ctx);
 }
 
 void build_tiles(depo_ctx *ctx, std::vector<TileDev> &tiles) {
@@ -1214,9 +1221,12 @@ depo_status depo_set_kernel_config(depo_ctx *ctx, int32_t targets_per_lane, int3
     ctx->drop_graph();
     return DEPO_OK;
   }
-  if (mode < DEPO_PAIR_PLAIN || mode > DEPO_PAIR_SYMMETRIC)
+  if (mode < DEPO_PAIR_PLAIN || mode > DEPO_PAIR_SYMMETRIC_INT || mode == DEPO_PAIR_P3M)
     return ctx->fail(DEPO_E_INVALID, "unknown pair-kernel mode %d", mode);
-  CoulombConfig c{targets_per_lane, waves, block, mode != DEPO_PAIR_PLAIN, mode == DEPO_PAIR_SYMMETRIC};
+  const bool sym = mode == DEPO_PAIR_SYMMETRIC || mode == DEPO_PAIR_SYMMETRIC_INT;
+  CoulombConfig c{targets_per_lane, waves, block, mode != DEPO_PAIR_PLAIN, sym, mode == DEPO_PAIR_SYMMETRIC_INT};
+  if (c.int_rec && !(ctx->p.L >= 2.0 * ctx->p.R))
+    return ctx->fail(DEPO_E_INVALID, "integer source records need L >= 2R (y and z within 2^31 x quanta)");
   if (c.symmetric) {
     if (ctx->fp64() || !coulomb_sym_supported(c))
       return ctx->fail(DEPO_E_INVALID, "unsupported symmetric pair-kernel configuration (%d, %d, %d)", targets_per_lane,
@@ -1233,6 +1243,7 @@ depo_status depo_set_kernel_config(depo_ctx *ctx, int32_t targets_per_lane, int3
   ctx->p3m_use = false;
   ctx->use_graph = use_graph != 0;
   ctx->drop_graph();
+  set_record_format(ctx);
   if (ctx->seeded) {
     std::vector<TileDev> tiles;
     build_tiles(ctx, tiles);

@@ -45,7 +45,14 @@ __device__ __forceinline__ void fx_add(unsigned long long *acc, int64_t i, doubl
   atomicAdd(acc + i, (unsigned long long)__double2ll_rn(v * scale));
 }
 
-template <int IPL, int W, bool REACT>
+// y or z difference of two records: float records subtract; integer records (bit patterns of
+// int32 x-quanta counts) subtract exactly and convert.
+template <bool INTREC> __device__ __forceinline__ float rdiff(float a, float b) {
+  if constexpr (INTREC) return (float)(__float_as_int(a) - __float_as_int(b));
+  else return a - b;
+}
+
+template <int IPL, int W, bool REACT, bool INTREC>
 __device__ __forceinline__ void ring_item(const SymItem &it, const JSrc<float> *__restrict__ js,
                                           const float *__restrict__ jr, double scale,
                                           unsigned long long *__restrict__ accx, unsigned long long *__restrict__ accy,
@@ -98,8 +105,8 @@ __device__ __forceinline__ void ring_item(const SymItem &it, const JSrc<float> *
       for (int k = 0; k < IPL; ++k) {
         if (k == kskip) continue;
         const float dx = sdiff(xi[k], s.x);
-        const float dy = yi[k] - s.y;
-        const float dz = zi[k] - s.z;
+        const float dy = rdiff<INTREC>(yi[k], s.y);
+        const float dz = rdiff<INTREC>(zi[k], s.z);
         const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, 1.0f)));
         nearmask |= __builtin_amdgcn_ballot_w64(r2 < near2);
         const float inv = __builtin_amdgcn_rsqf(r2);
@@ -142,8 +149,8 @@ __device__ __forceinline__ void ring_item(const SymItem &it, const JSrc<float> *
 #pragma unroll
         for (int k = 0; k < IPL; ++k) {
           const float dx = sdiff(xi[k], s.x);
-          const float dy = yi[k] - s.y;
-          const float dz = zi[k] - s.z;
+          const float dy = rdiff<INTREC>(yi[k], s.y);
+          const float dz = rdiff<INTREC>(zi[k], s.z);
           const float r2 = dx * dx + dy * dy + dz * dz;
           const float dd = ri[k] + rj;
           const float rc2 = fmaxf(r2, dd * dd);
@@ -195,7 +202,7 @@ __device__ __forceinline__ void ring_item(const SymItem &it, const JSrc<float> *
   }
 }
 
-template <int IPL, int W>
+template <int IPL, int W, bool INTREC>
 __global__ __launch_bounds__(64 * W) void k_coulomb_sym(const SymItem *__restrict__ items,
                                                         const JSrc<float> *__restrict__ js,
                                                         const float *__restrict__ jr,
@@ -209,9 +216,9 @@ __global__ __launch_bounds__(64 * W) void k_coulomb_sym(const SymItem *__restric
   const SymItem it = items[blockIdx.x];
   const double scale = fx_scale[it.sample];
   if (it.j0 == it.i0)
-    ring_item<IPL, W, false>(it, js, jr, scale, accx, accy, accz, near2, src, srad);
+    ring_item<IPL, W, false, INTREC>(it, js, jr, scale, accx, accy, accz, near2, src, srad);
   else
-    ring_item<IPL, W, true>(it, js, jr, scale, accx, accy, accz, near2, src, srad);
+    ring_item<IPL, W, true, INTREC>(it, js, jr, scale, accx, accy, accz, near2, src, srad);
 }
 
 // Fixed-point totals back to pair sums; the accumulators are cleared for the next evaluation.
@@ -252,10 +259,15 @@ void launch_coulomb_sym(const State<float> &st, const Phys &ph, int n_diag, int 
                         hipStream_t s) {
   const float near2 = (float)ph.near2;
   const int n_items = n_diag + n_off;
-#define X(I, W)                                                                                            \
-  if (n_items > 0 && cfg.ipl == I && cfg.waves == W)                                                       \
-    hipLaunchKernelGGL((k_coulomb_sym<I, W>), dim3(n_items), dim3(64 * W), 0, s, st.items, st.js, st.jr,   \
-                       st.fx_scale, st.accx, st.accy, st.accz, near2);
+#define X(I, W)                                                                                              \
+  if (n_items > 0 && cfg.ipl == I && cfg.waves == W) {                                                       \
+    if (cfg.int_rec)                                                                                         \
+      hipLaunchKernelGGL((k_coulomb_sym<I, W, true>), dim3(n_items), dim3(64 * W), 0, s, st.items, st.js,    \
+                         st.jr, st.fx_scale, st.accx, st.accy, st.accz, near2);                              \
+    else                                                                                                     \
+      hipLaunchKernelGGL((k_coulomb_sym<I, W, false>), dim3(n_items), dim3(64 * W), 0, s, st.items, st.js,   \
+                         st.jr, st.fx_scale, st.accx, st.accy, st.accz, near2);                              \
+  }
   DEPO_COULOMB_SYM_CASES(X)
 #undef X
   if (ph.N > 0)

@@ -139,8 +139,21 @@ __global__ __launch_bounds__(256) void k_prepare(State<Real> st, Phys ph, int mo
   if (mode & P_COULOMB) {
     JSrc<Real> js;
     js.x = px;
-    js.y = Real(((double)as_signed(py) + (double)ry) * ph.yz_over_x);
-    js.z = Real(((double)as_signed(pz) + (double)rz) * ph.yz_over_x);
+    const double yx = ((double)as_signed(py) + (double)ry) * ph.yz_over_x;
+    const double zx = ((double)as_signed(pz) + (double)rz) * ph.yz_over_x;
+    if constexpr (sizeof(Real) == 4) {
+      if (ph.flags & F_INT_RECORDS) {
+        // |y| < R: within +-2^31 x quanta for L >= 2R
+        js.y = __int_as_float((int32_t)fmin(fmax(rint(yx), -2147483647.0), 2147483647.0));
+        js.z = __int_as_float((int32_t)fmin(fmax(rint(zx), -2147483647.0), 2147483647.0));
+      } else {
+        js.y = Real(yx);
+        js.z = Real(zx);
+      }
+    } else {
+      js.y = Real(yx);
+      js.z = Real(zx);
+    }
     js.q = alive ? Real(st.samples[s].charge_scale * st.qb[i] / ph.q_ref) : Real(0);
     st.js[i] = js;
   }

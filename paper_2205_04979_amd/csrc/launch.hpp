@@ -27,6 +27,7 @@ struct CoulombConfig {
   int block;   // sources per compensated block
   bool compensated;  // Kahan accumulation of the block sums (FP32); plain sums otherwise
   bool symmetric = false;  // FP32: each unordered pair once, reaction on the source (Newton's third law)
+  bool int_rec = false;    // symmetric FP32: y and z of the source records as 32-bit integers in x quanta
 };
 template <class Real>
 void launch_coulomb(const State<Real> &st, const Phys &ph, int n_tiles, const CoulombConfig &cfg, hipStream_t s);

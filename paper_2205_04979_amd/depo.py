@@ -27,7 +27,7 @@ FLAG_BITS = {
 PHASES = ("prepare", "cells", "coulomb", "short_range", "finish")
 
 
-PAIR_PLAIN, PAIR_KAHAN, PAIR_SYMMETRIC, PAIR_P3M = 0, 1, 2, 3
+PAIR_PLAIN, PAIR_KAHAN, PAIR_SYMMETRIC, PAIR_P3M, PAIR_SYMMETRIC_INT = 0, 1, 2, 3, 4
 
 
 class DepoError(RuntimeError):
@@ -257,7 +257,7 @@ class Simulation(Context):
 
     def set_kernel_config(self, targets_per_lane: int, waves: int, block: int, mode=None, use_graph: bool = True,
                           compensated: Optional[bool] = None):
-        """Pair-kernel shape and mode: PAIR_PLAIN, PAIR_KAHAN or PAIR_SYMMETRIC (FP32).  ``mode=None`` selects
+        """Pair-kernel shape and mode: PAIR_PLAIN, PAIR_KAHAN, PAIR_SYMMETRIC or PAIR_SYMMETRIC_INT (FP32).  ``mode=None`` selects
         the one-sided Kahan mode in FP32 and plain in FP64 (before any call the library runs the symmetric
         mode, shape (4, 2, 64), in FP32).  ``compensated`` (bool) is accepted in place of ``mode`` for the
         one-sided modes.  The FP32 adjoint uses the symmetric pair adjoint when the mode is symmetric."""

@@ -73,11 +73,12 @@ P3M_65K = dict(mesh_x=128, mesh_yz=64, alpha_h=0.5, rmax_alpha=3.5)
 def p3m65k():
     """P3M sums S_i (lattice sum over x images by the P3M oracle, Appendix A.2.4) of every particle of the
     65,536-particle workload at its seeded positions, with the benchmark's mesh (128 x 128 x 128 padded,
-    alpha h = 0.5, r_max = 3.5 / alpha), and the normaliser sum_j |a_ij| of the direct sum."""
+    alpha h = 0.5, r_max = 3.5 / alpha), the normaliser sum_j |a_ij| of the direct sum and each particle's
+    distance to its nearest neighbour."""
     from oracle import p3m as op3m
     from oracle.sim import OracleSim
     from synthetic import make_workload
-    from tests.oracle_pool import pooled_coulomb_scale
+    from tests.oracle_pool import pooled_coulomb_scale, pooled_nearest
     w = make_workload("single-65k")
     f = w.field()
     t0 = time.perf_counter()
@@ -94,8 +95,9 @@ def p3m65k():
     print(f"short range: {time.perf_counter() - t0:.1f} s", flush=True)
     sim = OracleSim(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, evaluate=False)
     scale = pooled_coulomb_scale(sim, np.arange(w.n_particles))
-    print(f"normaliser: {time.perf_counter() - t0:.1f} s", flush=True)
-    np.savez_compressed(os.path.join(HERE, "p3m_single65k_seed.npz"), S=long + short, scale=scale,
+    r_min = pooled_nearest(sim, np.arange(w.n_particles))
+    print(f"normaliser and nearest sources: {time.perf_counter() - t0:.1f} s", flush=True)
+    np.savez_compressed(os.path.join(HERE, "p3m_single65k_seed.npz"), S=long + short, scale=scale, r_min=r_min,
                         config=np.array([c["mesh_x"], c["mesh_yz"], c["alpha_h"], c["rmax_alpha"]]),
                         digest=np.array(input_digest(w, f)))
     print("wrote p3m_single65k_seed.npz", flush=True)

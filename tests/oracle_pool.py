@@ -33,6 +33,27 @@ def _scale_chunk(targets):
     return coulomb_magnitude_sum(_SIM, np.asarray(targets, dtype=np.int64))
 
 
+def _check_chunk(targets):
+    t = np.asarray(targets, dtype=np.int64)
+    a = OracleSim.accelerations(_SIM, t, chunk=_CHUNK)
+    return np.concatenate([a, coulomb_magnitude_sum(_SIM, t)[:, None], nearest_distance(_SIM, t)[:, None]], axis=1)
+
+
+def nearest_distance(sim: OracleSim, targets) -> np.ndarray:
+    """Centre distance from each target to its nearest alive particle of the same sample (minimum image in x)."""
+    out = np.full(len(targets), np.inf)
+    for k, i in enumerate(targets):
+        s = sim.sample[i]
+        b, e = sim.offsets[s], sim.offsets[s + 1]
+        src = np.arange(b, e)
+        src = src[sim.alive[src] & (src != i)]
+        if src.size:
+            r = sim.x[i] - sim.x[src]
+            r[:, 0] -= sim.L * np.round(r[:, 0] / sim.L)
+            out[k] = np.sqrt(np.min(np.sum(r * r, axis=1)))
+    return out
+
+
 def coulomb_magnitude_sum(sim: OracleSim, targets) -> np.ndarray:
     """sum_j |a_ij| over the Coulomb pairs of each target (alive sources of its own sample, j != i)."""
     out = np.zeros(len(targets))
@@ -77,6 +98,23 @@ def pooled_coulomb_scale(sim: OracleSim, targets, processes=None) -> np.ndarray:
     """``coulomb_magnitude_sum`` on a pool of forked processes."""
     res = _map(_scale_chunk, sim, targets, processes, 4, 0)
     return np.concatenate(res) if res else np.zeros(0)
+
+
+def _nearest_chunk(targets):
+    return nearest_distance(_SIM, np.asarray(targets, dtype=np.int64))
+
+
+def pooled_nearest(sim: OracleSim, targets, processes=None) -> np.ndarray:
+    """``nearest_distance`` on a pool of forked processes."""
+    res = _map(_nearest_chunk, sim, targets, processes, 4, 0)
+    return np.concatenate(res) if res else np.zeros(0)
+
+
+def pooled_force_check(sim: OracleSim, targets, processes=None, chunk: int = 8):
+    """Per target: the oracle's acceleration (3 columns), sum_j |a_ij| of its Coulomb pairs and the distance to
+    its nearest source, on a pool of forked processes."""
+    res = _map(_check_chunk, sim, targets, processes, 4, chunk)
+    return np.concatenate(res, axis=0) if res else np.zeros((0, 5))
 
 
 class PooledOracle(OracleSim):
