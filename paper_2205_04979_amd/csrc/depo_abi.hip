@@ -540,6 +540,50 @@ depo_status build_samples(depo_ctx *ctx, const depo_sample_params *sp, const dou
   return DEPO_OK;
 }
 
+// Everything on the device besides the particle state itself that a seeded or restored state
+// needs: sample ids and table, neighbour counts, the tile and item lists of the pair kernels, the
+// fixed-point scales and zeroed accumulators, the P3M charge mesh and histogram (zeroed) and its
+// Green's function, a clear error flag.  build_samples and set_charge_bounds have run.  Synchronises.
+template <class Real> depo_status upload_tables(depo_ctx *ctx, hipStream_t s) {
+  State<Real> &st = state<Real>(ctx);
+  const size_t N = (size_t)ctx->N;
+  std::vector<int32_t> sid(N), zeros_i(N, 0);
+  for (int k = 0; k < ctx->S; ++k)
+    for (int64_t i = ctx->off[k]; i < ctx->off[k + 1]; ++i) sid[i] = k;
+  std::vector<TileDev> tiles;
+  build_tiles(ctx, tiles);
+  ctx->n_tiles = (int)tiles.size();
+  HIP_TRY(hipMemcpyAsync(st.sid, sid.data(), N * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(st.nbr, zeros_i.data(), N * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(st.samples, ctx->samples.data(), ctx->S * sizeof(SampleDev), hipMemcpyHostToDevice, s));
+  if (!tiles.empty())
+    HIP_TRY(hipMemcpyAsync(st.tiles, tiles.data(), tiles.size() * sizeof(TileDev), hipMemcpyHostToDevice, s));
+  const int32_t zero[16] = {0};
+  HIP_TRY(hipMemcpyAsync(st.err, zero, 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (!ctx->fp64()) {
+    depo_status u = upload_fx_scale(ctx, s);
+    if (u == DEPO_OK && ctx->ccfg.symmetric) u = upload_items(ctx);
+    if (u != DEPO_OK) return u;
+    launch_clear_int((int32_t *)ctx->sf.accx, 2 * N, s);
+    launch_clear_int((int32_t *)ctx->sf.accy, 2 * N, s);
+    launch_clear_int((int32_t *)ctx->sf.accz, 2 * N, s);
+  }
+  if (ctx->p3m_cfg) {
+    if (depo_status u = upload_p3m_scale(ctx, s); u != DEPO_OK) return u;
+    const P3mDev &m = ctx->pm;
+    launch_clear_int((int32_t *)m.qmesh, 2 * (size_t)m.nx * m.nc * m.nc, s);
+    launch_clear_int(m.counts, (size_t)m.ncx * m.ncy * m.ncy, s);
+    if (!ctx->p3m_green) {
+      p3m_setup_green(m, ctx->p.L, kP3mImages, sizeof(Real) == 4, s);
+      ctx->p3m_green = true;
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  return DEPO_OK;
+}
+
 template <class Real>
 depo_status do_seed(depo_ctx *ctx, const depo_sample_params *sp, const double *hx, const double *hv,
                     const double *hd, const double *hq, hipStream_t s) {
@@ -555,10 +599,8 @@ depo_status do_seed(depo_ctx *ctx, const depo_sample_params *sp, const double *h
   }
   std::vector<Pos> px(N), py(N), pz(N);
   std::vector<Real> rx(N), ry(N), rz(N);   // remainders of the positions beyond the fixed-point values
-  std::vector<int32_t> sid(N), zeros_i(N, 0);
+  std::vector<int32_t> zeros_i(N, 0);
   std::vector<double> zeros_d(N, 0.0);
-  for (int k = 0; k < ctx->S; ++k)
-    for (int64_t i = ctx->off[k]; i < ctx->off[k + 1]; ++i) sid[i] = k;
   for (int64_t i = 0; i < N; ++i) {
     const double x = hx[3 * i], y = hx[3 * i + 1], z = hx[3 * i + 2];
     if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z))
@@ -596,10 +638,8 @@ depo_status do_seed(depo_ctx *ctx, const depo_sample_params *sp, const double *h
   if (stt != DEPO_OK) return stt;
   ctx->sp.assign(sp, sp + ctx->S);
   ctx->ph.N = (int32_t)N;
+  set_charge_bounds(ctx, hd, hq);
   State<Real> &st = state<Real>(ctx);
-  std::vector<TileDev> tiles;
-  build_tiles(ctx, tiles);
-  ctx->n_tiles = (int)tiles.size();
   const size_t nb = (size_t)N;
   HIP_TRY(hipMemcpyAsync(st.px, px.data(), nb * sizeof(Pos), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(st.py, py.data(), nb * sizeof(Pos), hipMemcpyHostToDevice, s));
@@ -611,8 +651,6 @@ depo_status do_seed(depo_ctx *ctx, const depo_sample_params *sp, const double *h
   HIP_TRY(hipMemcpyAsync(st.qb, hq, nb * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(st.ell, zeros_d.data(), nb * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(st.dep, zeros_i.data(), nb * 4, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(st.sid, sid.data(), nb * 4, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(st.nbr, zeros_i.data(), nb * 4, hipMemcpyHostToDevice, s));
   std::vector<Real> vbuf;
   if (hv) {
     vbuf.resize(nb);
@@ -623,32 +661,9 @@ depo_status do_seed(depo_ctx *ctx, const depo_sample_params *sp, const double *h
       HIP_TRY(hipStreamSynchronize(s));
     }
   }
-  HIP_TRY(hipMemcpyAsync(st.samples, ctx->samples.data(), ctx->S * sizeof(SampleDev), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(st.tiles, tiles.data(), tiles.size() * sizeof(TileDev), hipMemcpyHostToDevice, s));
   const int32_t zero[16] = {0};
   HIP_TRY(hipMemcpyAsync(st.nstep, zero, 4, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(st.err, zero, 4, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  set_charge_bounds(ctx, hd, hq);
-  if (!ctx->fp64()) {
-    depo_status u = upload_fx_scale(ctx, s);
-    if (u == DEPO_OK && ctx->ccfg.symmetric) u = upload_items(ctx);
-    if (u != DEPO_OK) return u;
-    launch_clear_int((int32_t *)ctx->sf.accx, 2 * (size_t)N, s);
-    launch_clear_int((int32_t *)ctx->sf.accy, 2 * (size_t)N, s);
-    launch_clear_int((int32_t *)ctx->sf.accz, 2 * (size_t)N, s);
-  }
-  if (ctx->p3m_cfg) {
-    if (depo_status u = upload_p3m_scale(ctx, s); u != DEPO_OK) return u;
-    const P3mDev &m = ctx->pm;
-    launch_clear_int((int32_t *)m.qmesh, 2 * (size_t)m.nx * m.nc * m.nc, s);
-    launch_clear_int(m.counts, (size_t)m.ncx * m.ncy * m.ncy, s);
-    if (!ctx->p3m_green) {
-      p3m_setup_green(m, ctx->p.L, kP3mImages, sizeof(Real) == 4, s);
-      ctx->p3m_green = true;
-    }
-    HIP_TRY(hipGetLastError());
-  }
+  if (depo_status u = upload_tables<Real>(ctx, s); u != DEPO_OK) return u;
   // v^0 = u_f(x^0) when no velocity is given, before the initial force evaluation at x^0
   // (collision damping reads v^0 of the neighbours)
   if (!hv) launch_finish<Real>(st, ctx->ph, F_FLUID_ONLY, s);
@@ -811,17 +826,11 @@ template <class Real> depo_status do_upload(depo_ctx *ctx, const void *blob, siz
   depo_status r = build_samples(ctx, sp.data(), d.data());
   if (r != DEPO_OK) return r;
   ctx->sp = sp;
-  if (!ctx->fp64()) {
+  ctx->ph.N = (int32_t)N;
+  {
     std::vector<double> qb(N);
     std::memcpy(qb.data(), q + N * 8, N * 8);
     set_charge_bounds(ctx, d.data(), qb.data());
-    if ((r = upload_fx_scale(ctx, s)) != DEPO_OK) return r;
-  }
-  if (ctx->p3m_cfg) {
-    std::vector<double> qb(N);
-    std::memcpy(qb.data(), q + N * 8, N * 8);
-    set_charge_bounds(ctx, d.data(), qb.data());
-    if ((r = upload_p3m_scale(ctx, s)) != DEPO_OK) return r;
   }
   auto put = [&](void *dst, size_t n) -> depo_status {
     HIP_TRY(hipMemcpyAsync(dst, p, n, hipMemcpyHostToDevice, s));
@@ -835,10 +844,11 @@ template <class Real> depo_status do_upload(depo_ctx *ctx, const void *blob, siz
   for (double *a : {st.d, st.qb, st.ell})
     if ((r = put(a, N * 8)) != DEPO_OK) return r;
   if ((r = put(st.dep, N * 4)) != DEPO_OK) return r;
-  HIP_TRY(hipMemcpyAsync(st.samples, ctx->samples.data(), ctx->S * sizeof(SampleDev), hipMemcpyHostToDevice, s));
   const int32_t ns = h.nstep;
   HIP_TRY(hipMemcpyAsync(st.nstep, &ns, 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
+  // the tables a context that was never seeded lacks (sample ids, pair-kernel work lists, ...)
+  if ((r = upload_tables<Real>(ctx, s)) != DEPO_OK) return r;
   // refresh the Coulomb source radii
   launch_prepare<Real>(st, ctx->ph, P_SEED | P_COULOMB, s);
   HIP_TRY(hipGetLastError());

@@ -424,6 +424,42 @@ def test_fp32_bitwise_deterministic_and_checkpoint_roundtrip(cfg):
         sim.state_upload(blob[:-8])
 
 
+@pytest.mark.parametrize("p3m", [False, True])
+def test_checkpoint_restores_into_a_fresh_context_on_a_dirty_workspace(p3m):
+    """A checkpoint written by one context and restored into another that was never seeded, whose workspace
+    is a block the caching allocator hands back full of 0xFF bytes (stale memory): the restore rebuilds
+    every table seeding builds (sample ids, pair-kernel work lists, zeroed accumulators, P3M histogram and
+    charge mesh), so both contexts then step bitwise alike (FP32 default pair mode, or P3M)."""
+    import torch
+    from paper_2205_04979_amd.depo import Simulation
+    w = make_workload("single-65k", n=3000, field_n=32)
+    f = w.field()
+    cfg = dict(mesh_x=32, mesh_yz=16, alpha_h=0.5, rmax_alpha=3.5) if p3m else None
+    say("case: checkpoint into a fresh context on a dirty workspace, p3m =", p3m)
+    src = Simulation(w.params, w.offsets, f.shape[:3], real_bytes=4, p3m=cfg)
+    src.init_field(f)
+    src.seed(w.sample_params, w.x, w.d, w.qbase)
+    src.step(5)
+    blob = src.state_download()
+    nbytes = src._ws.numel()
+    torch.cuda.synchronize()
+    dirty = torch.full((nbytes,), 0xFF, dtype=torch.uint8, device="cuda")
+    lo, hi = dirty.data_ptr(), dirty.data_ptr() + dirty.numel()
+    torch.cuda.synchronize()
+    del dirty
+    dst = Simulation(w.params, w.offsets, f.shape[:3], real_bytes=4, p3m=cfg)
+    if not (lo <= dst._ws.data_ptr() < hi):
+        pytest.skip("the caching allocator did not hand back the dirtied block")
+    dst.init_field(f)
+    dst.state_upload(blob)
+    src.step(7)
+    dst.step(7)
+    a, b = src.read(), dst.read()
+    for k in ("x", "v", "a", "dep_step"):
+        assert np.array_equal(a[k], b[k]), k
+    assert src.tally() == dst.tally()
+
+
 @pytest.mark.parametrize("cfg", [(1, 8, 32), (4, 2, 64, 2), (4, 2, 64, 4)])
 def test_graph_replay_equals_direct_launch(cfg):
     """The captured step (forked into the pair-sum branch and the cell + short-range branch) gives
