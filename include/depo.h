@@ -135,6 +135,13 @@ typedef struct {
 const char *depo_status_string(int status);
 
 /* Create a context from validated parameters.  Host only, touches no GPU.
+ * The parameters are those of the particle-phase model of Appendix A.2: the gas
+ * (viscosity and density, Eq. part_source), the particle material density, the
+ * soft-sphere contact of Appendix A.2.2 (restitution e_pp, contact duration
+ * tau_col_steps time steps, stiffness ratio kr_over_k = k_r/k), the van der Waals
+ * saturation gap delta_min of Appendix A.2.3, the vacuum permittivity of Coulomb's
+ * law (Eq. coulomb), the rebound law of Section 4.4 (Eq. CoR: E_young, delta_c,
+ * acont_coef), and the pipe of Section 2.1 (radius R, periodic length L, Re_tau).
  * Returns DEPO_E_INVALID (with *out = NULL) for non-positive or non-finite
  * lengths, densities, viscosity or dt, e_pp outside (0, 1], tau_col_steps < 1,
  * real_bytes not 4 or 8, unknown flag bits, reserved != 0 or a negative or
@@ -164,17 +171,30 @@ depo_status depo_workspace_bytes(const depo_ctx *ctx, size_t *bytes);
  * library's counters on the default stream and waits for it. */
 depo_status depo_bind(depo_ctx *ctx, void *d_work, size_t bytes);
 
-/* Upload the carrier-gas velocity on the node grid declared by
+/* Upload the carrier-gas velocity u_f on the node grid declared by
  * depo_set_layout: h_uvw[nx][ny][nz][3] (z fastest), copied and converted
- * to the working precision.  Synchronises the stream. */
+ * to the working precision; it stays frozen while the particles move.  This is
+ * the carrier flow of Section 2.1 and Appendix A.1 that the paper takes from its
+ * DNS; any field on the grid is accepted (for instance a synthetic turbulent pipe
+ * field: mean profile plus random Fourier modes, zero outside the pipe), and the
+ * particles see it through the interpolation u_f[x_p] of Appendix A.2.1
+ * (trilinear here).  DEPO_E_INVALID for a non-finite value (nothing is kept);
+ * DEPO_E_STATE before depo_bind.  Synchronises the stream. */
 depo_status depo_init_field(depo_ctx *ctx, const double *h_uvw, depo_stream stream);
 
-/* Seed the particles: per-sample parameters sp[n_samples]; positions
- * h_x3[N][3] with 0 <= x < L (x is wrapped) and y^2 + z^2 < R^2; diameters
- * h_d[N] in (0, R/4); base charges h_qbase[N].  h_v3[N][3] may be NULL, in
- * which case each particle starts at the local fluid velocity.  Computes the
- * initial acceleration (all forces at the seeded positions) and resets the
- * tally and the step counter.  Synchronises the stream. */
+/* Seed the particles (Section 2.1: particles distributed at random in the pipe,
+ * each Monte Carlo sample with its own uncertain inputs): per-sample parameters
+ * sp[n_samples] (charge scale xi, Hamaker constant A = zeta A_0, temperature T of
+ * Sections 2.1 and 4.4); positions h_x3[N][3] with 0 <= x < L (x is wrapped) and
+ * y^2 + z^2 < R^2; diameters h_d[N] in (0, R/4); base charges h_qbase[N], so that
+ * particle i of sample s carries q_i = sp[s].charge_scale * h_qbase[i] (with
+ * h_qbase = q_max(d) this is the charge xi q_max of Eq. 1).  h_v3[N][3] may be
+ * NULL, in which case each particle starts at the local fluid velocity.  Positions
+ * are stored as fixed point plus a remainder, so they are kept to the input's
+ * precision.  Computes the initial acceleration (all forces at the seeded
+ * positions) and resets the tally and the step counter.  DEPO_E_INVALID (nothing
+ * changed) for a non-finite or out-of-range value; DEPO_E_STATE before the field
+ * is uploaded.  Synchronises the stream. */
 depo_status depo_seed(depo_ctx *ctx, const depo_sample_params *sp, const double *h_x3,
                       const double *h_v3, const double *h_d, const double *h_qbase,
                       depo_stream stream);
