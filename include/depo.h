@@ -331,6 +331,25 @@ depo_status depo_adjoint_workspace_bytes(const depo_ctx *ctx, int32_t n_steps, i
 depo_status depo_adjoint(depo_ctx *ctx, int32_t n_steps, int32_t ckpt_every, const double *h_weights,
                          double *h_grad, void *d_adj_work, size_t bytes, depo_stream stream);
 
+/* depo_adjoint in two halves, for callers that need J before they know the weights (an autograd
+ * function: J in its forward pass, the weights = incoming gradient in its backward pass).
+ *
+ * depo_adjoint_forward: the forward run of depo_adjoint (same preconditions and errors, except the
+ * weights): n_steps steps from the seeded state, storing checkpoints and the Coulomb tape in
+ * d_adj_work (caller-owned, depo_adjoint_workspace_bytes() bytes, 256-byte aligned, kept alive and
+ * unchanged until the backward call).  The context ends at step n_steps exactly as after
+ * depo_step(n_steps), so the tally can be read; it records one pending reverse sweep.
+ * Synchronises the stream.
+ *
+ * depo_adjoint_backward: the reverse sweep of the pending forward run for weights h_weights[S]
+ * (finite), h_grad[S][3] as for depo_adjoint; the context is back at the forward's final state
+ * afterwards.  Consumes the pending sweep.  DEPO_E_STATE when there is none, or when any call that
+ * changes the state, the parameters, the field or the kernel configuration (seed, step, restore,
+ * eval, set_*, bind, init_field, another adjoint forward) came in between.  Synchronises. */
+depo_status depo_adjoint_forward(depo_ctx *ctx, int32_t n_steps, int32_t ckpt_every, void *d_adj_work,
+                                 size_t bytes, depo_stream stream);
+depo_status depo_adjoint_backward(depo_ctx *ctx, const double *h_weights, double *h_grad, depo_stream stream);
+
 /* Low-fidelity model: the one-dimensional Eulerian deposition model of
  * Appendix B (particle momentum equation with turbophoresis, image-charge and
  * wall-cohesion forces, Eq. mom_modified with implicit drag; constant-flux

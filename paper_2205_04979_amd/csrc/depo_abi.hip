@@ -105,6 +105,14 @@ struct depo_ctx {
   hipStream_t cap_side = nullptr;               // the graph's short-range branch
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool use_graph = true;
+  // state generation: every call that changes the particle state, the parameters, the field or the
+  // kernel configuration advances it; a pending reverse sweep belongs to one generation
+  uint64_t gen = 0;
+  bool adj_pending = false;
+  uint64_t adj_gen = 0;
+  int adj_n = 0, adj_ce = 0;
+  void *adj_ws = nullptr;
+  size_t adj_bytes = 0;
 
   bool fp64() const { return p.real_bytes == 8; }
   depo_status fail(depo_status st, const char *fmt, ...) {
@@ -913,14 +921,57 @@ size_t carve_adjoint(const depo_ctx *ctx, char *base, int n_steps, int n_ckpt, i
   return o;
 }
 
+// Forward run of the adjoint: the n steps from the seeded state with checkpoints every ce steps and
+// the Coulomb tape, into the caller's workspace; leaves the context at step n and records the
+// pending reverse sweep.
 template <class Real>
-depo_status do_adjoint(depo_ctx *ctx, int n, int ce, const double *hw, double *hg, void *dws, size_t bytes,
-                       hipStream_t s) {
+depo_status do_adjoint_forward(depo_ctx *ctx, int n, int ce, void *dws, size_t bytes, hipStream_t s) {
   AdjPlan<Real> pl;
   const int K = (n + ce - 1) / ce;
   const size_t need = carve_adjoint<Real>(ctx, nullptr, n, K, ce, pl);
   if (bytes < need) return ctx->fail(DEPO_E_CAPACITY, "adjoint workspace needs %zu bytes", need);
   carve_adjoint<Real>(ctx, (char *)dws, n, K, ce, pl);
+  const State<Real> &st = state<Real>(ctx);
+  const int N = (int)ctx->N;
+  const bool coul = (ctx->p.flags & DEPO_COULOMB) != 0;
+  const size_t nb = (size_t)N * sizeof(Real);
+  // the raw Coulomb sums of a step to its Coulomb-tape entry
+  auto sums_to_tape = [&](int k) -> hipError_t {
+    Real *t = pl.ctape + (size_t)k * 3 * N;
+    hipError_t e = hipMemcpyAsync(t, st.cx, nb, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(t + N, st.cy, nb, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(t + 2 * (size_t)N, st.cz, nb, hipMemcpyDeviceToDevice, s);
+    return e;
+  };
+  // forward run with checkpoints every ce steps; the pair sums of every step that does not end
+  // at a checkpoint (or at the final state) are kept, so that the per-segment recomputation
+  // of the reverse sweep runs only the O(N) kernels
+  for (int k = 0; k < n; ++k) {
+    if (k % ce == 0) launch_tape_store<Real>(st, pl.ckpt[k / ce], N, false, s);
+    // the same step as depo_step (the captured graph, when enabled); the step counter is set below
+    if (depo_status r = run_steps<Real>(ctx, 1, s); r != DEPO_OK) return r;
+    if (coul && k % ce != ce - 1 && k != n - 1) HIP_TRY(sums_to_tape((k / ce) * (ce - 1) + k % ce));
+  }
+  launch_tape_store<Real>(st, pl.fin, N, true, s);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  ctx->nstep = n;
+  ctx->adj_pending = true;
+  ctx->adj_gen = ctx->gen;
+  ctx->adj_n = n;
+  ctx->adj_ce = ce;
+  ctx->adj_ws = dws;
+  ctx->adj_bytes = bytes;
+  return check_err<Real>(ctx, s);
+}
+
+// Reverse sweep over the workspace of the pending forward run; the context ends at the forward's
+// final state.
+template <class Real> depo_status do_adjoint_backward(depo_ctx *ctx, const double *hw, double *hg, hipStream_t s) {
+  const int n = ctx->adj_n, ce = ctx->adj_ce;
+  AdjPlan<Real> pl;
+  const int K = (n + ce - 1) / ce;
+  carve_adjoint<Real>(ctx, (char *)ctx->adj_ws, n, K, ce, pl);
   const State<Real> &st = state<Real>(ctx);
   const Phys &ph = ctx->ph;
   const int N = (int)ctx->N;
@@ -931,15 +982,8 @@ depo_status do_adjoint(depo_ctx *ctx, int n, int ce, const double *hw, double *h
   const double scale = (wmax > 0.0 && mmax > 0.0) ? 1.0 / (wmax * mmax) : 1.0;
   HIP_TRY(hipMemcpyAsync(pl.ad.weights, hw, ctx->S * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
-  // the raw Coulomb sums of a step to and from its Coulomb-tape entry
   const size_t nb = (size_t)N * sizeof(Real);
-  auto sums_to_tape = [&](int k) -> hipError_t {
-    Real *t = pl.ctape + (size_t)k * 3 * N;
-    hipError_t e = hipMemcpyAsync(t, st.cx, nb, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(t + N, st.cy, nb, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(t + 2 * (size_t)N, st.cz, nb, hipMemcpyDeviceToDevice, s);
-    return e;
-  };
+  // the raw Coulomb sums of a step back from its Coulomb-tape entry
   auto sums_from_tape = [&](int k) -> hipError_t {
     const Real *t = pl.ctape + (size_t)k * 3 * N;
     hipError_t e = hipMemcpyAsync(st.cx, t, nb, hipMemcpyDeviceToDevice, s);
@@ -947,16 +991,6 @@ depo_status do_adjoint(depo_ctx *ctx, int n, int ce, const double *hw, double *h
     if (e == hipSuccess) e = hipMemcpyAsync(st.cz, t + 2 * (size_t)N, nb, hipMemcpyDeviceToDevice, s);
     return e;
   };
-  // forward run with checkpoints every ce steps; the pair sums of every step that does not end
-  // at a checkpoint (or at the final state) are kept, so that the per-segment recomputation
-  // below runs only the O(N) kernels
-  for (int k = 0; k < n; ++k) {
-    if (k % ce == 0) launch_tape_store<Real>(st, pl.ckpt[k / ce], N, false, s);
-    // the same step as depo_step (the captured graph, when enabled); the step counter is set below
-    if (depo_status r = run_steps<Real>(ctx, 1, s); r != DEPO_OK) return r;
-    if (coul && k % ce != ce - 1 && k != n - 1) HIP_TRY(sums_to_tape((k / ce) * (ce - 1) + k % ce));
-  }
-  launch_tape_store<Real>(st, pl.fin, N, true, s);
   launch_adj_init<Real>(st, ph, pl.ad, pl.ad.weights, scale, s);
   auto rebuild_cells = [&]() {
     if (sr) {
@@ -1078,6 +1112,7 @@ const char *depo_last_error(const depo_ctx *ctx) { return ctx ? ctx->err.c_str()
 depo_status depo_set_layout(depo_ctx *ctx, int32_t n_samples, const int64_t *offsets, int32_t nx, int32_t ny,
                             int32_t nz) {
   if (!ctx) return DEPO_E_INVALID;
+  ++ctx->gen;   // a pending adjoint reverse sweep no longer applies
   if (n_samples < 1 || !offsets) return ctx->fail(DEPO_E_INVALID, "need n_samples >= 1 and offsets");
   if (offsets[0] != 0) return ctx->fail(DEPO_E_INVALID, "offsets[0] must be 0");
   for (int s = 0; s < n_samples; ++s)
@@ -1147,6 +1182,7 @@ depo_status depo_workspace_bytes(const depo_ctx *ctx, size_t *bytes) {
 
 depo_status depo_bind(depo_ctx *ctx, void *d_work, size_t bytes) {
   if (!ctx) return DEPO_E_INVALID;
+  ++ctx->gen;   // a pending adjoint reverse sweep no longer applies
   if (!ctx->has_layout) return ctx->fail(DEPO_E_STATE, "set the layout before binding");
   if (!d_work || ((uintptr_t)d_work % kAlign) != 0) return ctx->fail(DEPO_E_INVALID, "workspace must be 256-byte aligned");
   if (bytes < ctx->ws_need) return ctx->fail(DEPO_E_CAPACITY, "workspace needs %zu bytes", ctx->ws_need);
@@ -1165,6 +1201,7 @@ depo_status depo_bind(depo_ctx *ctx, void *d_work, size_t bytes) {
 
 depo_status depo_init_field(depo_ctx *ctx, const double *h_uvw, depo_stream stream) {
   if (!ctx) return DEPO_E_INVALID;
+  ++ctx->gen;   // a pending adjoint reverse sweep no longer applies
   if (!ctx->bound) return ctx->fail(DEPO_E_STATE, "bind a workspace first");
   if (!h_uvw) return ctx->fail(DEPO_E_INVALID, "null field");
   depo_status r = DISPATCH(do_init_field, ctx, h_uvw, (hipStream_t)stream);
@@ -1175,6 +1212,7 @@ depo_status depo_init_field(depo_ctx *ctx, const double *h_uvw, depo_stream stre
 depo_status depo_seed(depo_ctx *ctx, const depo_sample_params *sp, const double *h_x3, const double *h_v3,
                       const double *h_d, const double *h_qbase, depo_stream stream) {
   if (!ctx) return DEPO_E_INVALID;
+  ++ctx->gen;   // a pending adjoint reverse sweep no longer applies
   if (!ctx->bound || !ctx->field_ready) return ctx->fail(DEPO_E_STATE, "bind a workspace and upload the field first");
   if (!sp || (ctx->N > 0 && (!h_x3 || !h_d || !h_qbase))) return ctx->fail(DEPO_E_INVALID, "null input array");
   ctx->seeded = false;
@@ -1183,6 +1221,7 @@ depo_status depo_seed(depo_ctx *ctx, const depo_sample_params *sp, const double 
 
 depo_status depo_set_sample_params(depo_ctx *ctx, const depo_sample_params *sp, depo_stream stream) {
   if (!ctx) return DEPO_E_INVALID;
+  ++ctx->gen;   // a pending adjoint reverse sweep no longer applies
   if (!ctx->seeded) return ctx->fail(DEPO_E_STATE, "seed first");
   if (!sp) return ctx->fail(DEPO_E_INVALID, "null sample parameters");
   for (int k = 0; k < ctx->S; ++k) {
@@ -1207,6 +1246,7 @@ depo_status depo_set_sample_params(depo_ctx *ctx, const depo_sample_params *sp, 
 
 depo_status depo_step(depo_ctx *ctx, int32_t n_steps, depo_stream stream) {
   if (!ctx) return DEPO_E_INVALID;
+  ++ctx->gen;   // a pending adjoint reverse sweep no longer applies
   if (!ctx->seeded) return ctx->fail(DEPO_E_STATE, "seed first");
   if (n_steps < 0) return ctx->fail(DEPO_E_INVALID, "n_steps must be >= 0");
   if ((int64_t)ctx->nstep + n_steps > (int64_t)INT32_MAX - 1) return ctx->fail(DEPO_E_INVALID, "step counter overflow");
@@ -1215,6 +1255,7 @@ depo_status depo_step(depo_ctx *ctx, int32_t n_steps, depo_stream stream) {
 
 depo_status depo_step_timed(depo_ctx *ctx, int32_t n_steps, depo_stream stream, double *h_phase_ms) {
   if (!ctx) return DEPO_E_INVALID;
+  ++ctx->gen;   // a pending adjoint reverse sweep no longer applies
   if (!ctx->seeded) return ctx->fail(DEPO_E_STATE, "seed first");
   if (n_steps < 1 || n_steps > 100000 || !h_phase_ms) return ctx->fail(DEPO_E_INVALID, "need 1..100000 steps and an output array");
   if ((int64_t)ctx->nstep + n_steps > (int64_t)INT32_MAX - 1) return ctx->fail(DEPO_E_INVALID, "step counter overflow");
@@ -1224,6 +1265,7 @@ depo_status depo_step_timed(depo_ctx *ctx, int32_t n_steps, depo_stream stream, 
 depo_status depo_set_kernel_config(depo_ctx *ctx, int32_t targets_per_lane, int32_t waves, int32_t block,
                                    int32_t mode, int32_t use_graph) {
   if (!ctx) return DEPO_E_INVALID;
+  ++ctx->gen;   // a pending adjoint reverse sweep no longer applies
   if (mode == DEPO_PAIR_P3M) {
     if (!ctx->p3m_cfg) return ctx->fail(DEPO_E_INVALID, "P3M is not configured (depo_set_p3m before the layout)");
     ctx->p3m_use = true;
@@ -1267,6 +1309,7 @@ depo_status depo_set_kernel_config(depo_ctx *ctx, int32_t targets_per_lane, int3
 
 depo_status depo_eval_accel(depo_ctx *ctx, depo_stream stream) {
   if (!ctx) return DEPO_E_INVALID;
+  ++ctx->gen;   // a pending adjoint reverse sweep no longer applies
   if (!ctx->seeded) return ctx->fail(DEPO_E_STATE, "seed first");
   hipStream_t s = (hipStream_t)stream;
   if (ctx->fp64()) {
@@ -1312,6 +1355,7 @@ depo_status depo_state_download(depo_ctx *ctx, void *h_blob, size_t bytes, depo_
 
 depo_status depo_state_upload(depo_ctx *ctx, const void *h_blob, size_t bytes, depo_stream stream) {
   if (!ctx) return DEPO_E_INVALID;
+  ++ctx->gen;   // a pending adjoint reverse sweep no longer applies
   if (!ctx->bound || !ctx->field_ready) return ctx->fail(DEPO_E_STATE, "bind a workspace and upload the field first");
   if (!h_blob) return ctx->fail(DEPO_E_INVALID, "null blob");
   return DISPATCH(do_upload, ctx, h_blob, bytes, (hipStream_t)stream);
@@ -1332,25 +1376,47 @@ depo_status depo_adjoint_workspace_bytes(const depo_ctx *ctx, int32_t n_steps, i
   return DEPO_OK;
 }
 
-depo_status depo_adjoint(depo_ctx *ctx, int32_t n_steps, int32_t ckpt_every, const double *h_weights,
-                         double *h_grad, void *d_adj_work, size_t bytes, depo_stream stream) {
+depo_status depo_adjoint_forward(depo_ctx *ctx, int32_t n_steps, int32_t ckpt_every, void *d_adj_work, size_t bytes,
+                                 depo_stream stream) {
   if (!ctx) return DEPO_E_INVALID;
   if (!ctx->seeded) return ctx->fail(DEPO_E_STATE, "seed first");
   if (ctx->nstep != 0) return ctx->fail(DEPO_E_STATE, "the adjoint starts from the seeded state (step 0)");
   if (!(ctx->p.flags & DEPO_SOFT_TALLY)) return ctx->fail(DEPO_E_INVALID, "the adjoint needs DEPO_SOFT_TALLY");
   if (ctx->p3m_use) return ctx->fail(DEPO_E_INVALID, "the adjoint differentiates the direct Coulomb sum; select a direct mode");
   if (n_steps < 1 || ckpt_every < 1 || ckpt_every > n_steps) return ctx->fail(DEPO_E_INVALID, "need 1 <= ckpt_every <= n_steps");
+  if (!d_adj_work || ((uintptr_t)d_adj_work % kAlign) != 0) return ctx->fail(DEPO_E_INVALID, "adjoint workspace must be 256-byte aligned");
+  ctx->adj_pending = false;
+  ++ctx->gen;
+  return DISPATCH(do_adjoint_forward, ctx, n_steps, ckpt_every, d_adj_work, bytes, (hipStream_t)stream);
+}
+
+depo_status depo_adjoint_backward(depo_ctx *ctx, const double *h_weights, double *h_grad, depo_stream stream) {
+  if (!ctx) return DEPO_E_INVALID;
+  if (!ctx->adj_pending || ctx->adj_gen != ctx->gen)
+    return ctx->fail(DEPO_E_STATE, "no pending adjoint forward run (or the state changed since)");
   if (!h_weights || !h_grad) return ctx->fail(DEPO_E_INVALID, "null weights or gradient array");
   for (int k = 0; k < ctx->S; ++k)
     if (!std::isfinite(h_weights[k])) return ctx->fail(DEPO_E_INVALID, "weight %d not finite", k);
-  if (!d_adj_work || ((uintptr_t)d_adj_work % kAlign) != 0) return ctx->fail(DEPO_E_INVALID, "adjoint workspace must be 256-byte aligned");
-  return DISPATCH(do_adjoint, ctx, n_steps, ckpt_every, h_weights, h_grad, d_adj_work, bytes, (hipStream_t)stream);
+  ctx->adj_pending = false;
+  return DISPATCH(do_adjoint_backward, ctx, h_weights, h_grad, (hipStream_t)stream);
+}
+
+depo_status depo_adjoint(depo_ctx *ctx, int32_t n_steps, int32_t ckpt_every, const double *h_weights,
+                         double *h_grad, void *d_adj_work, size_t bytes, depo_stream stream) {
+  if (!ctx) return DEPO_E_INVALID;
+  if (!h_weights || !h_grad) return ctx->fail(DEPO_E_INVALID, "null weights or gradient array");
+  for (int k = 0; k < ctx->S; ++k)
+    if (!std::isfinite(h_weights[k])) return ctx->fail(DEPO_E_INVALID, "weight %d not finite", k);
+  depo_status r = depo_adjoint_forward(ctx, n_steps, ckpt_every, d_adj_work, bytes, stream);
+  if (r != DEPO_OK) return r;
+  return depo_adjoint_backward(ctx, h_weights, h_grad, stream);
 }
 
 static bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
 
 depo_status depo_set_p3m(depo_ctx *ctx, int32_t mesh_x, int32_t mesh_yz, double alpha_h, double rmax_alpha) {
   if (!ctx) return DEPO_E_INVALID;
+  ++ctx->gen;   // a pending adjoint reverse sweep no longer applies
   if (ctx->has_layout) return ctx->fail(DEPO_E_STATE, "configure P3M before depo_set_layout");
   if (!pow2_in(mesh_x, 16, 1024) || !pow2_in(mesh_yz, 16, 512) || !(alpha_h > 0.0 && alpha_h <= 2.0) ||
       !(rmax_alpha >= 2.0 && rmax_alpha <= 6.0))

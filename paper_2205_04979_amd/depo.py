@@ -87,6 +87,8 @@ _SIGS = {
     "depo_state_upload": (C.c_int, [_P, _P, C.c_size_t, _P]),
     "depo_adjoint_workspace_bytes": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
     "depo_adjoint": (C.c_int, [_P, C.c_int32, C.c_int32, _DP, _DP, _P, C.c_size_t, _P]),
+    "depo_adjoint_forward": (C.c_int, [_P, C.c_int32, C.c_int32, _P, C.c_size_t, _P]),
+    "depo_adjoint_backward": (C.c_int, [_P, _DP, _DP, _P]),
     "depo_set_p3m": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_double, C.c_double]),
     "depo_lf_solve": (C.c_int, [C.POINTER(Params), C.c_int64, _P, _P, _P, C.c_int32, C.c_int32, _P, _P]),
 }
@@ -299,19 +301,38 @@ class Simulation(Context):
         buf = C.create_string_buffer(bytes(blob), len(blob))
         self.check(self._L.depo_state_upload(self._h, buf, len(blob), self._stream(stream)), "depo_state_upload")
 
-    def adjoint(self, n_steps: int, ckpt_every: int, weights=None, stream=None) -> np.ndarray:
-        """Run n_steps from the seeded state and return dJ/d(charge_scale, hamaker, temperature), shape (S, 3)."""
+    def _adjoint_workspace(self, n_steps: int, ckpt_every: int):
         import torch
         n = C.c_size_t()
         self.check(self._L.depo_adjoint_workspace_bytes(self._h, int(n_steps), int(ckpt_every), C.byref(n)),
                    "depo_adjoint_workspace_bytes")
+        ws = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        return ws, (ws.data_ptr() + 255) // 256 * 256, n.value
+
+    def adjoint(self, n_steps: int, ckpt_every: int, weights=None, stream=None) -> np.ndarray:
+        """Run n_steps from the seeded state and return dJ/d(charge_scale, hamaker, temperature), shape (S, 3)."""
+        ws, aligned, nbytes = self._adjoint_workspace(n_steps, ckpt_every)
         w = np.ones(self.s) if weights is None else _f64(weights, (self.s,))
         g = np.zeros((self.s, 3))
-        ws = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
-        aligned = (ws.data_ptr() + 255) // 256 * 256
         self.check(self._L.depo_adjoint(self._h, int(n_steps), int(ckpt_every), _dptr(w), _dptr(g),
-                                        C.c_void_p(aligned), n.value, self._stream(stream)), "depo_adjoint")
+                                        C.c_void_p(aligned), nbytes, self._stream(stream)), "depo_adjoint")
         del ws
+        return g
+
+    def adjoint_forward(self, n_steps: int, ckpt_every: int, stream=None):
+        """Forward half of the adjoint: run n_steps from the seeded state storing checkpoints.  Returns the
+        device workspace, which must stay alive until ``adjoint_backward``."""
+        ws, aligned, nbytes = self._adjoint_workspace(n_steps, ckpt_every)
+        self.check(self._L.depo_adjoint_forward(self._h, int(n_steps), int(ckpt_every), C.c_void_p(aligned), nbytes,
+                                                self._stream(stream)), "depo_adjoint_forward")
+        return ws
+
+    def adjoint_backward(self, weights, stream=None) -> np.ndarray:
+        """Reverse half: dJ/d(charge_scale, hamaker, temperature) of J = sum_s w_s J_s, shape (S, 3)."""
+        w = _f64(weights, (self.s,))
+        g = np.zeros((self.s, 3))
+        self.check(self._L.depo_adjoint_backward(self._h, _dptr(w), _dptr(g), self._stream(stream)),
+                   "depo_adjoint_backward")
         return g
 
 
@@ -333,6 +354,9 @@ def lf_solve(params: dict, d, q, A, n_wall: int = 800, n_core: int = 800, device
     return out.cpu().numpy()
 
 
+_DEPOSITION_FN = None
+
+
 def _autograd_function():
     import torch
 
@@ -341,21 +365,23 @@ def _autograd_function():
         charge scale, Hamaker constant and temperature (hand-written adjoint in the library).
 
         forward(charge_scale[S], hamaker[S], temperature[S], sim, seed, n_steps, ckpt_every) with
-        ``seed = dict(x=..., d=..., qbase=..., v=None)`` reseeds ``sim`` with these parameters."""
+        ``seed = dict(x=..., d=..., qbase=..., v=None)`` reseeds ``sim`` with these parameters and runs the
+        checkpointed forward only; backward runs the reverse sweep with the incoming gradient as the
+        per-sample weights.  Between the two, ``sim`` must not be seeded, stepped or reconfigured."""
 
         @staticmethod
         def forward(ctx, charge_scale, hamaker, temperature, sim, seed, n_steps, ckpt_every):
             sp = torch.stack([charge_scale, hamaker, temperature], 1).detach().cpu().double().numpy()
             sim.seed(sp, seed["x"], seed["d"], seed["qbase"], v=seed.get("v"))
-            grad = sim.adjoint(n_steps, ckpt_every)
+            ctx.sim = sim
+            ctx.workspace = sim.adjoint_forward(n_steps, ckpt_every)
             J = torch.tensor([t["j_soft"] for t in sim.tally()], dtype=torch.float64)
-            ctx.save_for_backward(torch.from_numpy(grad))
             return J.to(charge_scale.device)
 
         @staticmethod
         def backward(ctx, gJ):
-            (grad,) = ctx.saved_tensors
-            g = gJ.detach().cpu().double()[:, None] * grad
+            g = torch.from_numpy(ctx.sim.adjoint_backward(gJ.detach().cpu().double().numpy()))
+            ctx.workspace = None
             dev = gJ.device
             return g[:, 0].to(dev), g[:, 1].to(dev), g[:, 2].to(dev), None, None, None, None
 
@@ -363,6 +389,9 @@ def _autograd_function():
 
 
 def __getattr__(name):
+    global _DEPOSITION_FN
     if name == "DepositionFn":
-        return _autograd_function()
+        if _DEPOSITION_FN is None:
+            _DEPOSITION_FN = _autograd_function()
+        return _DEPOSITION_FN
     raise AttributeError(name)

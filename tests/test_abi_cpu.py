@@ -144,12 +144,17 @@ def test_kernel_config_validation(depo):
     assert L.depo_set_kernel_config(ctx._h, 4, 2, 64, 2, 1) == depo.OK
     assert L.depo_set_kernel_config(ctx._h, 1, 2, 64, 2, 1) == depo.E_INVALID      # 128-target items
     assert L.depo_set_kernel_config(ctx._h, 1, 8, 32, 2, 1) == depo.E_INVALID      # rounds are 64 sources
-    assert L.depo_set_kernel_config(ctx._h, 1, 8, 64, 3, 1) == depo.E_INVALID      # unknown mode
+    assert L.depo_set_kernel_config(ctx._h, 1, 8, 64, 3, 1) == depo.E_INVALID      # P3M not configured
     assert L.depo_set_kernel_config(ctx._h, 1, 8, 64, -1, 1) == depo.E_INVALID
+    # symmetric mode with integer source records (4): the same shapes, FP32 only
+    assert L.depo_set_kernel_config(ctx._h, 4, 2, 64, 4, 1) == depo.OK
+    assert L.depo_set_kernel_config(ctx._h, 1, 8, 32, 4, 1) == depo.E_INVALID
+    assert L.depo_set_kernel_config(ctx._h, 1, 8, 64, 5, 1) == depo.E_INVALID      # unknown mode
     ctx64 = depo.Context(physical_params(), 8)
     assert L.depo_set_kernel_config(ctx64._h, 2, 8, 32, 0, 1) == depo.E_INVALID
     assert L.depo_set_kernel_config(ctx64._h, 1, 4, 16, 0, 0) == depo.OK
     assert L.depo_set_kernel_config(ctx64._h, 1, 8, 64, 2, 1) == depo.E_INVALID
+    assert L.depo_set_kernel_config(ctx64._h, 4, 2, 64, 4, 1) == depo.E_INVALID
 
 
 def test_adjoint_host_validation(depo):
@@ -170,6 +175,16 @@ def test_adjoint_host_validation(depo):
     w = (C.c_double * 2)(1.0, 1.0)
     g = (C.c_double * 6)()
     assert L.depo_adjoint(ctx._h, 10, 5, w, g, C.c_void_p(256), 1 << 30, None) == depo.E_STATE  # not seeded
+    # the two halves: the forward needs a seeded state, the backward a pending forward run
+    assert L.depo_adjoint_forward(ctx._h, 10, 5, C.c_void_p(256), 1 << 30, None) == depo.E_STATE
+    assert L.depo_adjoint_backward(ctx._h, w, g, None) == depo.E_STATE
+    assert b"pending" in L.depo_last_error(ctx._h)
+
+
+def test_deposition_function_is_one_class(depo):
+    """The autograd Function is built once and the same class is returned on every lookup."""
+    pytest.importorskip("torch")
+    assert depo.DepositionFn is depo.DepositionFn
 
 
 def test_adjoint_workspace_holds_the_coulomb_tape(depo):

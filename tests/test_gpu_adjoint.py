@@ -264,6 +264,18 @@ def test_autograd_function_backward():
     assert np.allclose(cs.grad.numpy(), w.numpy() * g[:, 0], rtol=1e-12)
     assert np.allclose(A.grad.numpy(), w.numpy() * g[:, 1], rtol=1e-12)
     assert np.all(T.grad.numpy() == 0.0)
+    # forward runs only the checkpointed forward: J equals a plain forward run's, and a state change
+    # between forward and backward (here one more step) makes the backward an error, not a wrong answer
+    from paper_2205_04979_amd.depo import DepoError, E_STATE
+    J2 = DepositionFn.apply(cs, A, T, sim, dict(x=x, d=d, qbase=q, v=v0), n, ce)
+    ref = gpu_sim(p, f, off, 8)
+    ref.seed(sp, x, d, q, v=v0)
+    ref.step(n)
+    assert np.array_equal(J2.detach().numpy(), np.array([t["j_soft"] for t in ref.tally()]))
+    sim.step(1)
+    with pytest.raises(DepoError) as ei:
+        J2.sum().backward()
+    assert ei.value.status == E_STATE
 
 
 FORCE_SETS = {
