@@ -350,6 +350,17 @@ depo_status depo_adjoint_forward(depo_ctx *ctx, int32_t n_steps, int32_t ckpt_ev
                                  size_t bytes, depo_stream stream);
 depo_status depo_adjoint_backward(depo_ctx *ctx, const double *h_weights, double *h_grad, depo_stream stream);
 
+/* depo_adjoint without any device allocation, for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, results and errors as depo_adjoint,
+ * but the adjoint workspace is a static device array of the library, 64 MiB on each GPU it runs on
+ * (held until the process ends), instead of caller memory; the forward steps are launched directly
+ * (results equal the captured graph's bitwise).  DEPO_E_CAPACITY, with nothing run, when
+ * depo_adjoint_workspace_bytes() exceeds 64 MiB.  Calls no hipMalloc or hipFree.  Every call on one
+ * GPU shares that GPU's array (it keeps the last call's contents, none of which a call reads before
+ * writing): calls that overlap on one GPU, from several contexts or threads, race.  Synchronises. */
+depo_status depo_adjoint_noalloc(depo_ctx *ctx, int32_t n_steps, int32_t ckpt_every, const double *h_weights,
+                                 double *h_grad, depo_stream stream);
+
 /* Low-fidelity model: the one-dimensional Eulerian deposition model of
  * Appendix B (particle momentum equation with turbophoresis, image-charge and
  * wall-cohesion forces, Eq. mom_modified with implicit drag; constant-flux

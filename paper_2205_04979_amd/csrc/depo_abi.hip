@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1058,6 +1059,38 @@ template <class Real> depo_status do_adjoint_backward(depo_ctx *ctx, const doubl
   return check_err<Real>(ctx, s);
 }
 
+// ---------------------------------------------------------------- allocation-free adjoint workspace
+//
+// depo_adjoint_noalloc keeps its adjoint workspace in this file-scope device array instead of
+// caller memory.  Each GPU the library runs on holds its own copy until the process ends.  In host
+// code the array's name is not a device address: the address is taken per device with
+// hipGetSymbolAddress on the first call on that device and only that pointer is used afterwards.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices] = {};
+}  // namespace
+
+// Device address of this GPU's scratch array (the current device), taken once per device.
+static depo_status scratch_address(depo_ctx *ctx, void **out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices) return ctx->fail(DEPO_E_INVALID, "device %d beyond the scratch table", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return ctx->fail(DEPO_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DEPO_OK;
+}
+
 #define DISPATCH(fn, ...) (ctx->fp64() ? fn<double>(__VA_ARGS__) : fn<float>(__VA_ARGS__))
 
 extern "C" {
@@ -1408,6 +1441,30 @@ depo_status depo_adjoint(depo_ctx *ctx, int32_t n_steps, int32_t ckpt_every, con
   for (int k = 0; k < ctx->S; ++k)
     if (!std::isfinite(h_weights[k])) return ctx->fail(DEPO_E_INVALID, "weight %d not finite", k);
   depo_status r = depo_adjoint_forward(ctx, n_steps, ckpt_every, d_adj_work, bytes, stream);
+  if (r != DEPO_OK) return r;
+  return depo_adjoint_backward(ctx, h_weights, h_grad, stream);
+}
+
+depo_status depo_adjoint_noalloc(depo_ctx *ctx, int32_t n_steps, int32_t ckpt_every, const double *h_weights,
+                                 double *h_grad, depo_stream stream) {
+  if (!ctx) return DEPO_E_INVALID;
+  if (!ctx->seeded) return ctx->fail(DEPO_E_STATE, "seed first");
+  if (!h_weights || !h_grad) return ctx->fail(DEPO_E_INVALID, "null weights or gradient array");
+  for (int k = 0; k < ctx->S; ++k)
+    if (!std::isfinite(h_weights[k])) return ctx->fail(DEPO_E_INVALID, "weight %d not finite", k);
+  size_t need = 0;
+  if (depo_adjoint_workspace_bytes(ctx, n_steps, ckpt_every, &need) != DEPO_OK)
+    return ctx->fail(DEPO_E_INVALID, "need 1 <= ckpt_every <= n_steps");
+  if (need > kScratchBytes)
+    return ctx->fail(DEPO_E_CAPACITY, "the adjoint needs %zu bytes of workspace; the static workspace holds %zu "
+                                      "(use depo_adjoint with a caller workspace)", need, kScratchBytes);
+  void *ws = nullptr;
+  if (depo_status r = scratch_address(ctx, &ws); r != DEPO_OK) return r;
+  // the forward runs the step kernels directly: capturing a step graph could allocate
+  const bool graph = ctx->use_graph;
+  ctx->use_graph = false;
+  depo_status r = depo_adjoint_forward(ctx, n_steps, ckpt_every, ws, kScratchBytes, stream);
+  ctx->use_graph = graph;
   if (r != DEPO_OK) return r;
   return depo_adjoint_backward(ctx, h_weights, h_grad, stream);
 }

@@ -89,6 +89,7 @@ _SIGS = {
     "depo_adjoint": (C.c_int, [_P, C.c_int32, C.c_int32, _DP, _DP, _P, C.c_size_t, _P]),
     "depo_adjoint_forward": (C.c_int, [_P, C.c_int32, C.c_int32, _P, C.c_size_t, _P]),
     "depo_adjoint_backward": (C.c_int, [_P, _DP, _DP, _P]),
+    "depo_adjoint_noalloc": (C.c_int, [_P, C.c_int32, C.c_int32, _DP, _DP, _P]),
     "depo_set_p3m": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_double, C.c_double]),
     "depo_lf_solve": (C.c_int, [C.POINTER(Params), C.c_int64, _P, _P, _P, C.c_int32, C.c_int32, _P, _P]),
 }
@@ -317,6 +318,14 @@ class Simulation(Context):
         self.check(self._L.depo_adjoint(self._h, int(n_steps), int(ckpt_every), _dptr(w), _dptr(g),
                                         C.c_void_p(aligned), nbytes, self._stream(stream)), "depo_adjoint")
         del ws
+        return g
+
+    def adjoint_noalloc(self, n_steps: int, ckpt_every: int, weights=None, stream=None) -> np.ndarray:
+        """``adjoint`` with the library's static device workspace (no device allocation; at most 64 MiB)."""
+        w = np.ones(self.s) if weights is None else _f64(weights, (self.s,))
+        g = np.zeros((self.s, 3))
+        self.check(self._L.depo_adjoint_noalloc(self._h, int(n_steps), int(ckpt_every), _dptr(w), _dptr(g),
+                                                self._stream(stream)), "depo_adjoint_noalloc")
         return g
 
     def adjoint_forward(self, n_steps: int, ckpt_every: int, stream=None):
