@@ -32,6 +32,7 @@ if ROOT not in sys.path:
 PEAK_FP32_VECTOR_TFLOPS = 157.3       # MI355X published FP32 vector peak (packed FP32 FMA)
 NONPACKED_FMA_TFLOPS = 78.6           # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz: one FMA per lane per cycle
 FLOPS_PER_PAIR = 20                   # customary N-body count per interaction
+HOST_CORE_SHARE = 16                  # host cores that go with one GPU on the benchmark machine
 
 
 def log(*a):
@@ -66,7 +67,8 @@ def cpu_baseline(w, field, n_targets: int):
     global _SIM
     from oracle.sim import OracleSim
     _SIM = OracleSim(w.params, field, w.x, w.d, w.qbase, w.offsets, w.sample_params, evaluate=False)
-    cores = min(16, len(os.sched_getaffinity(0)))
+    visible = len(os.sched_getaffinity(0))
+    cores = min(HOST_CORE_SHARE, visible)
     rng = np.random.default_rng(12345)
     n_targets = min(n_targets, w.n_particles)
     targets = np.sort(rng.choice(w.n_particles, n_targets, replace=False))
@@ -81,7 +83,8 @@ def cpu_baseline(w, field, n_targets: int):
     return dict(value=n_targets / wall, unit="particle-steps/s", cores=cores, kind="oracle",
                 sample=f"{which} of the {w.name} workload, one full step each "
                        f"(drag kicks, gather, all {w.n_particles} Coulomb sources, short-range and wall terms), "
-                       f"FP64 NumPy, {cores} processes",
+                       f"FP64 NumPy, {cores} processes on {cores} host cores (every core of this GPU's host share; "
+                       f"{visible} visible)",
                 seconds=wall)
 
 
@@ -98,7 +101,7 @@ def oracle_timings() -> dict:
     global _SIM
     from oracle.sim import OracleSim
     from synthetic import make_workload
-    cores = min(16, len(os.sched_getaffinity(0)))
+    cores = min(HOST_CORE_SHARE, len(os.sched_getaffinity(0)))
     out = {"cores": cores}
     w = make_workload("plain-1k")
     f = w.field()
@@ -157,39 +160,116 @@ def measured_traffic(shape):
     return None
 
 
-def batched_run(steps: int) -> dict:
-    """The 256-sample Monte Carlo batch (uneven sample sizes, one launch per kernel family, graph replay)."""
+def sequential_estimate(w, field, steps: int = 20, strata: int = 8, per_stratum: int = 2) -> dict:
+    """Per-step time of running the batch's samples one after another as single-sample simulations (the
+    plain single-sample step, library defaults, graph replay), estimated from a stratified subset: the
+    samples are sorted by size into equal strata, ``per_stratum`` of each (seeded choice) are timed over
+    ``steps`` steps, and each stratum's total is its size times the mean time of its picks."""
+    import torch
+    from paper_2205_04979_amd.depo import Simulation
+    sizes = np.diff(w.offsets)
+    order = np.argsort(sizes, kind="stable")
+    rng = np.random.default_rng(2024)
+    total_ms, picked = 0.0, []
+    for grp in np.array_split(order, strata):
+        picks = rng.choice(grp, min(per_stratum, grp.size), replace=False)
+        times = []
+        for s in picks:
+            b, e = int(w.offsets[s]), int(w.offsets[s + 1])
+            sim = Simulation(w.params, np.array([0, e - b]), field.shape[:3], real_bytes=4, device="cuda:0")
+            sim.init_field(field)
+            sim.seed(w.sample_params[s:s + 1], w.x[b:e], w.d[b:e], w.qbase[b:e])
+            sim.step(3)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(steps)
+            torch.cuda.synchronize()
+            times.append(1e3 * (time.perf_counter() - t0) / steps)
+            picked.append([int(s), e - b, round(times[-1], 4)])
+            sim.close()
+        total_ms += grp.size * float(np.mean(times))
+    return {"ms_per_step": round(total_ms, 4), "steps_timed_per_sample": steps,
+            "timed_samples": picked,
+            "method": f"{strata} size strata of the {w.n_samples} samples, {per_stratum} timed per stratum as "
+                      f"single-sample simulations; stratum total = its size x the mean of its picks"}
+
+
+def batched_run(steps: int = 0) -> dict:
+    """The 256-sample Monte Carlo batch (uneven sample sizes, one launch per kernel family, graph replay):
+    the whole run (``steps`` = 0: the workload's 1,000 steps) timed, against the same samples stepped one
+    after another as single-sample simulations (estimated from a stratified subset)."""
     import torch
     from paper_2205_04979_amd.autotune import autotune
     from paper_2205_04979_amd.depo import Simulation
     from synthetic import make_workload
     w = make_workload("batched-256")
     field = w.field()
-    log(f"[bench] batched-256: S={w.n_samples} N={w.n_particles}")
+    steps = steps or w.steps
+    log(f"[bench] batched-256: S={w.n_samples} N={w.n_particles}, {steps} steps timed")
     sim = Simulation(w.params, w.offsets, field.shape[:3], real_bytes=4, device="cuda:0")
     sim.init_field(field)
     sim.seed(w.sample_params, w.x, w.d, w.qbase)
     shape, _ = autotune(sim, steps=1)
+    sim.step(2)                       # warm the kernels up, then start the run from the seeded state
+    sim.seed(w.sample_params, w.x, w.d, w.qbase)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n_ph = 20
+    ph = sim.step_timed(n_ph)
+    ms = 1e3 * wall / steps
+    pairs = float(np.sum(np.diff(w.offsets).astype(np.float64) ** 2))
+    coul = ph["coulomb"] / n_ph
+    del sim
+    torch.cuda.empty_cache()
+    seq = sequential_estimate(w, field)
+    res = {"workload": w.name, "samples": w.n_samples, "particles": w.n_particles, "steps_timed": steps,
+           "wall_s": round(wall, 4), "ms_per_step": round(ms, 4),
+           "samples_per_s": round(w.n_samples * steps / (w.steps * wall), 4),
+           "sample_steps_per_s": round(w.n_samples * 1e3 / ms, 1),
+           "particle_steps_per_s": round(w.n_particles * 1e3 / ms, 1),
+           "coulomb_ms": round(coul, 4), "ordered_pairs_per_s": round(pairs / (coul * 1e-3), 1),
+           "pair_kernel_shape": list(shape),
+           "sequential_single_sample": seq,
+           "batched_speedup_over_sequential": round(seq["ms_per_step"] / ms, 3),
+           "note": (f"samples/s = {w.n_samples} samples / wall time of the {w.steps}-step run"
+                    + ("" if steps == w.steps else f" (scaled from {steps} timed steps)"))}
+    log(f"[bench] batched: {res}")
+    return res
+
+
+def large_run(steps: int = 5) -> dict:
+    """The 2^20-particle single sample with the direct O(N^2) Coulomb sums (the FP32 default pair kernel):
+    particle-steps/s over ``steps`` graph-replayed steps and the pair kernel's roofline fraction."""
+    import torch
+    from paper_2205_04979_amd.depo import Simulation
+    from synthetic import make_workload
+    w = make_workload("large-1m")
+    field = w.field()
+    log(f"[bench] large-1m direct: N={w.n_particles}, {steps} steps")
+    sim = Simulation(w.params, w.offsets, field.shape[:3], real_bytes=4, device="cuda:0")
+    sim.init_field(field)
+    sim.seed(w.sample_params, w.x, w.d, w.qbase)
     sim.step(2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ph = sim.step_timed(max(1, steps // 10))
-    n_tot = max(1, steps // 10)
-    ms = 1e3 * wall / steps
-    pairs = float(np.sum(np.diff(w.offsets).astype(np.float64) ** 2))
-    coul = ph["coulomb"] / n_tot
-    full = w.steps
-    res = {"workload": w.name, "samples": w.n_samples, "particles": w.n_particles, "steps_timed": steps,
-           "ms_per_step": round(ms, 4), "samples_per_s": round(w.n_samples / (full * ms * 1e-3), 4),
-           "sample_steps_per_s": round(w.n_samples * 1e3 / ms, 1),
-           "particle_steps_per_s": round(w.n_particles * 1e3 / ms, 1),
-           "coulomb_ms": round(coul, 4), "ordered_pairs_per_s": round(pairs / (coul * 1e-3), 1),
-           "pair_kernel_shape": list(shape),
-           "note": f"samples/s = {w.n_samples} samples / time of the full {full}-step run at the measured per-step time"}
-    log(f"[bench] batched: {res}")
+    ph = sim.step_timed(steps)
+    N = w.n_particles
+    coul = ph["coulomb"] / steps
+    achieved = float(N) * (N - 1) / 2.0 * FLOPS_PER_PAIR / (coul * 1e-3) / 1e12
+    res = {"workload": w.name, "particles": N, "steps_timed": steps, "ms_per_step": round(1e3 * wall / steps, 3),
+           "particle_steps_per_s": round(N * steps / wall, 1), "pair_kernel": pair_kernel_name((4, 2, 64, 2)),
+           "coulomb_ms": round(coul, 3), "achieved_tflops": round(achieved, 3),
+           "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
+           "frac_of_nonpacked_fma_peak": round(achieved / NONPACKED_FMA_TFLOPS, 4),
+           "phase_ms_per_step": {k: round(v / steps, 4) for k, v in ph.items()}}
+    log(f"[bench] large: {res}")
+    sim.close()
     del sim
     torch.cuda.empty_cache()
     return res
@@ -411,11 +491,13 @@ def main():
                     help="particles of the workload the CPU oracle steps once (capped at the workload size)")
     ap.add_argument("--kernel", default=None, help="pair-kernel shape ipl,waves,block (skips autotuning)")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--legs", default="single,batched,adjoint,rebound,plain,lf,p3m",
+    ap.add_argument("--legs", default="single,batched,adjoint,rebound,plain,lf,p3m,large",
                     help="which measurements to run: single (the headline), batched, adjoint, rebound, plain, lf, "
-                         "p3m")
-    ap.add_argument("--secondary-steps", type=int, default=100,
-                    help="steps timed for the batched Monte Carlo workload (0 disables it)")
+                         "p3m, large")
+    ap.add_argument("--secondary-steps", type=int, default=1000,
+                    help="steps timed for the batched Monte Carlo workload (its whole run is 1,000; 0 disables "
+                         "the secondary legs)")
+    ap.add_argument("--large-steps", type=int, default=5, help="steps timed in the 2^20-particle direct leg")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run one device-to-device copy of this size (reference for HBM counters)")
     ap.add_argument("--p3m-workloads", default=",".join(P3M_CONFIGS),
@@ -453,6 +535,8 @@ def main():
             out["lf"] = lf_run()
         if "p3m" in legs:
             out["p3m"] = p3m_run(args.p3m_steps, p3m_names)
+        if "large" in legs:
+            out["large"] = large_run(args.large_steps)
         print(json.dumps(out), flush=True)
         return
 
@@ -558,6 +642,8 @@ def main():
             out["lf"] = lf_run()
         if "p3m" in legs:
             out["p3m"] = p3m_run(args.p3m_steps, p3m_names)
+        if "large" in legs:
+            out["large"] = large_run(args.large_steps)
     if cb is not None:
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline"]["value"] = round(cb["value"], 2)
