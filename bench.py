@@ -498,6 +498,8 @@ def main():
                     help="steps timed for the batched Monte Carlo workload (its whole run is 1,000; 0 disables "
                          "the secondary legs)")
     ap.add_argument("--large-steps", type=int, default=5, help="steps timed in the 2^20-particle direct leg")
+    ap.add_argument("--clock-warmup-ms", type=float, default=200.0,
+                    help="GPU busy time (matrix products, not steps) right before the warm-up steps")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run one device-to-device copy of this size (reference for HBM counters)")
     ap.add_argument("--p3m-workloads", default=",".join(P3M_CONFIGS),
@@ -578,6 +580,17 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.clock_warmup_ms > 0:
+        # keep the GPU busy (plain matrix products, no simulation state touched) until the clocks have
+        # ramped up, so that a short timed region does not measure the ramp
+        a = torch.rand(2048, 2048, device="cuda:0")
+        b = torch.rand(2048, 2048, device="cuda:0")
+        t_w = time.perf_counter()
+        while time.perf_counter() - t_w < 1e-3 * args.clock_warmup_ms:
+            for _ in range(8):
+                a = torch.mm(a, b).clamp_(-1.0, 1.0)
+            torch.cuda.synchronize()
+        del a, b
     log(f"[bench] seeded N={N}; warmup {args.warmup} steps")
     if args.warmup:
         sim.step(args.warmup)
@@ -626,7 +639,7 @@ def main():
                    "alive_at_end": int(n_alive), "pair_kernel_shape": list(shape),
                    "autotune_ms_per_step": None if tune is None else {",".join(map(str, k)): round(v, 4) for k, v in tune.items()}, "ms_per_step_direct_launch_with_events": round(1e3 * wall_phases / p_steps, 5),
                    "phase_ms_per_step": {k: round(v / p_steps, 5) for k, v in phase_ms.items()},
-                   "phase_steps": p_steps},
+                   "phase_steps": p_steps, "clock_warmup_ms": args.clock_warmup_ms},
         "roofline": roofline,
     }
     if args.secondary_steps > 0 and args.workload == "single-65k":

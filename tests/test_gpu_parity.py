@@ -201,6 +201,53 @@ def test_short_range_pairs_across_cell_faces(real_bytes):
         assert np.max(np.linalg.norm(g["a"] - ora.a, axis=1) / (scale + 1e-3 * scale.max())) < 1e-4
 
 
+@pytest.mark.parametrize("real_bytes", [8, 4])
+def test_short_range_pairs_at_and_near_saturation_per_particle(real_bytes):
+    """Isolated pairs (contact and van der Waals cohesion only, Appendix A.2.2-A.2.3) with surface gaps from
+    a small overlap through the saturation gap delta_M = delta_min (k_r/k)^(1/4) up to near the d/4
+    cutoff, unequal and equal diameters, small relative velocities: every particle's acceleration is its
+    one pair force, compared with the oracle per particle relative to |a| alone.  FP64: 1e-12; FP32: 5e-6
+    (the gap is formed in FP64 from the fixed-point differences, the force in FP32)."""
+    from oracle.physics import vdw_saturation_gap
+    rng = np.random.default_rng(41)
+    p = physical_params(180.0, drag=False, coulomb=False, wall_image=False, wall_vdw=False)
+    R, L = p["R"], p["L"]
+    dm = vdw_saturation_gap(p)
+    factors = np.array([-40.0, -0.5, 0.0, 0.2, 0.9, 0.999, 1.001, 1.1, 3.0, 30.0, 100.0, 200.0])
+    n_pairs = 96
+    centres = []
+    while len(centres) < n_pairs:     # pair centres at least 0.3 mm apart, inside |y|, |z| < R/2
+        c = np.array([rng.uniform(0, L), rng.uniform(-0.5 * R, 0.5 * R), rng.uniform(-0.5 * R, 0.5 * R)])
+        if all(np.linalg.norm(c - o) > 3e-4 for o in centres):
+            centres.append(c)
+    x = np.zeros((2 * n_pairs, 3))
+    d = np.zeros(2 * n_pairs)
+    for k, c in enumerate(centres):
+        di, dj = (10e-6, 10e-6) if k % 2 == 0 else (rng.choice([5e-6, 20e-6]), 10e-6)
+        gap = factors[k % factors.size] * dm
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        sep = 0.5 * (di + dj) + gap
+        x[2 * k], x[2 * k + 1] = c + 0.5 * sep * u, c - 0.5 * sep * u
+        d[2 * k], d[2 * k + 1] = di, dj
+    x[:, 0] = np.mod(x[:, 0], L)
+    v0 = rng.normal(0.0, 0.01, (2 * n_pairs, 3))
+    q = np.zeros(2 * n_pairs)
+    sp = np.array([[1.0, 4e-19, 300.0]])
+    f = make_workload("plain-1k", n=4, field_n=16).field()
+    say("case: isolated pairs at and near saturation, fp", 8 * real_bytes)
+    sim, ora = seeded_pair(p, f, x, d, q, np.array([0, 2 * n_pairs]), sp, real_bytes, v0=v0)
+    g = sim.read()
+    assert np.array_equal(g["neighbours"], np.ones(2 * n_pairs, dtype=np.int32))
+    an = np.linalg.norm(ora.a, axis=1)
+    assert np.all(an > 0)
+    e = np.linalg.norm(g["a"] - ora.a, axis=1) / an
+    worst = int(np.argmax(e))
+    say(f"per particle: max {e.max():.3e} (pair {worst // 2}, gap / delta_M {factors[(worst // 2) % factors.size]}) "
+        f"median {np.median(e):.3e}")
+    assert e.max() < (1e-12 if real_bytes == 8 else 5e-6)
+
+
 def test_fp64_batched_samples_with_rebound():
     w = make_workload("batched-256", n_samples=5, n_lo=60, n_hi=300, field_n=32)
     f = w.field()
