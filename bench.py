@@ -33,6 +33,7 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3       # MI355X published FP32 vector peak (packe
 NONPACKED_FMA_TFLOPS = 78.6           # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz: one FMA per lane per cycle
 FLOPS_PER_PAIR = 20                   # customary N-body count per interaction
 HOST_CORE_SHARE = 16                  # host cores that go with one GPU on the benchmark machine
+REORDER = 16                          # steps between storage reorders in the batched, large and p3m legs
 
 
 def log(*a):
@@ -210,6 +211,7 @@ def batched_run(steps: int = 0) -> dict:
     sim.init_field(field)
     sim.seed(w.sample_params, w.x, w.d, w.qbase)
     shape, _ = autotune(sim, steps=1)
+    sim.set_reorder(REORDER)
     sim.step(2)                       # warm the kernels up, then start the run from the seeded state
     sim.seed(w.sample_params, w.x, w.d, w.qbase)
     torch.cuda.synchronize()
@@ -231,7 +233,7 @@ def batched_run(steps: int = 0) -> dict:
            "sample_steps_per_s": round(w.n_samples * 1e3 / ms, 1),
            "particle_steps_per_s": round(w.n_particles * 1e3 / ms, 1),
            "coulomb_ms": round(coul, 4), "ordered_pairs_per_s": round(pairs / (coul * 1e-3), 1),
-           "pair_kernel_shape": list(shape),
+           "pair_kernel_shape": list(shape), "reorder_every": REORDER,
            "sequential_single_sample": seq,
            "batched_speedup_over_sequential": round(seq["ms_per_step"] / ms, 3),
            "note": (f"samples/s = {w.n_samples} samples / wall time of the {w.steps}-step run"
@@ -250,6 +252,7 @@ def large_run(steps: int = 5) -> dict:
     field = w.field()
     log(f"[bench] large-1m direct: N={w.n_particles}, {steps} steps")
     sim = Simulation(w.params, w.offsets, field.shape[:3], real_bytes=4, device="cuda:0")
+    sim.set_reorder(REORDER)
     sim.init_field(field)
     sim.seed(w.sample_params, w.x, w.d, w.qbase)
     sim.step(2)
@@ -267,7 +270,7 @@ def large_run(steps: int = 5) -> dict:
            "coulomb_ms": round(coul, 3), "achieved_tflops": round(achieved, 3),
            "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
            "frac_of_nonpacked_fma_peak": round(achieved / NONPACKED_FMA_TFLOPS, 4),
-           "phase_ms_per_step": {k: round(v / steps, 4) for k, v in ph.items()}}
+           "phase_ms_per_step": {k: round(v / steps, 4) for k, v in ph.items()}, "reorder_every": REORDER}
     log(f"[bench] large: {res}")
     sim.close()
     del sim
@@ -449,11 +452,12 @@ def p3m_run(steps: int = 5, names=None) -> dict:
         w = make_workload(name)
         field = w.field()
         res = {"particles": w.n_particles, "mesh": [cfg["mesh_x"], 2 * cfg["mesh_yz"], 2 * cfg["mesh_yz"]],
-               "alpha_h": cfg["alpha_h"], "rmax_alpha": cfg["rmax_alpha"]}
+               "alpha_h": cfg["alpha_h"], "rmax_alpha": cfg["rmax_alpha"], "reorder_every": REORDER}
         for kind in ("p3m", "direct"):
             log(f"[bench] p3m leg: {name} {kind}")
             sim = Simulation(w.params, w.offsets, field.shape[:3], real_bytes=4, device="cuda:0",
                              p3m=cfg if kind == "p3m" else None)
+            sim.set_reorder(REORDER)
             sim.init_field(field)
             if kind == "direct":
                 sim.set_kernel_config(4, 2, 64, 2)
@@ -481,6 +485,7 @@ def p3m_run(steps: int = 5, names=None) -> dict:
 
 
 def main():
+    global REORDER
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
@@ -498,6 +503,9 @@ def main():
                     help="steps timed for the batched Monte Carlo workload (its whole run is 1,000; 0 disables "
                          "the secondary legs)")
     ap.add_argument("--large-steps", type=int, default=5, help="steps timed in the 2^20-particle direct leg")
+    ap.add_argument("--reorder", type=int, default=REORDER,
+                    help="steps between storage reorders into cell order in the batched, large and p3m legs "
+                         "(0: none); set after the autotuner has run")
     ap.add_argument("--clock-warmup-ms", type=float, default=200.0,
                     help="GPU busy time (matrix products, not steps) right before the warm-up steps")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -509,6 +517,7 @@ def main():
                     help="only time the FP64 oracle on the host cores (plain-1k in full, the large-1m force "
                          "check); no GPU")
     args = ap.parse_args()
+    REORDER = args.reorder
     p3m_names = args.p3m_workloads.split(",")
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the library has no multi-GPU path "

@@ -252,6 +252,19 @@ enum {
 depo_status depo_set_kernel_config(depo_ctx *ctx, int32_t targets_per_lane, int32_t waves, int32_t block,
                                    int32_t mode, int32_t use_graph);
 
+/* Storage order of the particles: with short-range forces on (a cell list is built every step),
+ * the per-particle state is permuted into the order of the last cell list at the start of every
+ * step that follows a multiple of `every` steps (0: never, the default), so that the cell-ordered
+ * walks and the field gather read contiguous memory.  Every sample keeps its slots (alive particles
+ * in cell order, then the removed ones), and the permutation is deterministic.  The library keeps
+ * the permutation: every host array it returns is in the caller's order, and checkpoint blobs carry
+ * it.  Sums whose order follows the storage (one-sided pair sums, short-range sums, tallies) then
+ * round differently from a run without reordering.  The reorder is part of the captured step and
+ * decided on the device from the step counter.  The smoothed-tally mode never reorders (the
+ * adjoint's stored states share one order).  Drops the captured step.  Host only; DEPO_E_INVALID
+ * outside 0..2^20. */
+depo_status depo_set_reorder(depo_ctx *ctx, int32_t every);
+
 /* P3M electrostatics (Appendix A.2.4, Eq. coulomb_force): the Coulomb sums
  * from a Gaussian split into a short-range direct part and a long-range mesh
  * part solved with FFTs, O(N log N).  It computes the lattice sum over all x

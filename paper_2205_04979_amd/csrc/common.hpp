@@ -87,7 +87,7 @@ enum : uint32_t {
 // integers in x quanta (bit patterns in the float fields) for the symmetric integer-record kernel.
 enum : uint32_t { F_INT_RECORDS = 1u << 16 };
 
-enum : uint32_t { ERR_NONFINITE = 1u };
+enum : uint32_t { ERR_NONFINITE = 1u, ERR_ORDER = 2u };
 
 template <class Real>
 struct State {
@@ -101,6 +101,7 @@ struct State {
   Real *sx, *sy, *sz;             // short-range accelerations
   double *d, *qb, *ell;
   int32_t *dep, *sid, *nbr;
+  int32_t *perm;                  // original index of the particle held in each slot (storage order)
   int32_t *cell_of, *cell_idx, *cell_count, *cell_start, *scan_part;
   JSrc<Real> *js;
   Real *jr;                       // radius in units of the x quantum
@@ -113,6 +114,14 @@ struct State {
   int32_t *nstep;
   uint32_t *err;
   double *tally;                  // [S][8]
+};
+
+// Second copy of the per-particle state that the storage reorder gathers into (same types).
+template <class Real> struct OrderScratch {
+  typename Prec<Real>::Pos *px, *py, *pz;
+  Real *rx, *ry, *rz, *vx, *vy, *vz, *ax, *ay, *az, *ux, *uy, *uz, *jr;
+  double *d, *qb, *ell;
+  int32_t *dep, *nbr, *perm;
 };
 
 // ---------------------------------------------------------------- fixed-point helpers

@@ -100,6 +100,9 @@ struct depo_ctx {
   Phys ph{};
   State<float> sf{};
   State<double> sd{};
+  OrderScratch<float> of{};
+  OrderScratch<double> od{};
+  int order_every = 0;        // steps between storage reorders (0: never)
   // captured step graph
   hipGraphExec_t gexec = nullptr;
   hipStream_t cap_stream = nullptr;
@@ -141,6 +144,10 @@ namespace {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+template <class Real> OrderScratch<Real> &order_scratch(depo_ctx *ctx);
+template <> OrderScratch<float> &order_scratch<float>(depo_ctx *ctx) { return ctx->of; }
+template <> OrderScratch<double> &order_scratch<double>(depo_ctx *ctx) { return ctx->od; }
+
 // Carve the workspace (base == nullptr: only size it).
 template <class Real>
 size_t carve(depo_ctx *ctx, char *base, State<Real> &st) {
@@ -164,6 +171,7 @@ size_t carve(depo_ctx *ctx, char *base, State<Real> &st) {
   st.dep = (int32_t *)take(N * 4);
   st.sid = (int32_t *)take(N * 4);
   st.nbr = (int32_t *)take(N * 4);
+  st.perm = (int32_t *)take(N * 4);
   st.cell_of = (int32_t *)take(N * 4);
   st.cell_idx = (int32_t *)take(N * 4);
   st.cell_count = (int32_t *)take((size_t)ctx->cell_cap * 4);
@@ -196,6 +204,21 @@ size_t carve(depo_ctx *ctx, char *base, State<Real> &st) {
     m.table = (float2 *)take(2049 * sizeof(float2));   // 2,048 intervals + the terminating (0, 0)
     ctx->p3m_qscale = (double *)take(64);
     m.q_scale = ctx->p3m_qscale;
+  }
+  {
+    OrderScratch<Real> &sc = order_scratch<Real>(ctx);
+    sc.px = (Pos *)take(N * sizeof(Pos));
+    sc.py = (Pos *)take(N * sizeof(Pos));
+    sc.pz = (Pos *)take(N * sizeof(Pos));
+    Real **reals[] = {&sc.rx, &sc.ry, &sc.rz, &sc.vx, &sc.vy, &sc.vz, &sc.ax, &sc.ay, &sc.az,
+                      &sc.ux, &sc.uy, &sc.uz, &sc.jr};
+    for (Real **r : reals) *r = (Real *)take(N * sizeof(Real));
+    sc.d = (double *)take(N * 8);
+    sc.qb = (double *)take(N * 8);
+    sc.ell = (double *)take(N * 8);
+    sc.dep = (int32_t *)take(N * 4);
+    sc.nbr = (int32_t *)take(N * 4);
+    sc.perm = (int32_t *)take(N * 4);
   }
   st.field = (typename Prec<Real>::Vec4 *)take((size_t)ctx->nx * ctx->ny * ctx->nz * sizeof(typename Prec<Real>::Vec4));
   st.nstep = (int32_t *)take(64);
@@ -388,8 +411,17 @@ int prepare_mode(const depo_ctx *ctx) {
   return m;
 }
 
+// The storage reorder kernels of a step (they act only on the steps that follow a multiple of
+// order_every steps).  Not in the smoothed-tally mode, whose adjoint stores states in one order,
+// and only with a cell list, which the short-range forces build every step.
+template <class Real> void enqueue_order(depo_ctx *ctx, hipStream_t s) {
+  if (ctx->order_every <= 0 || !short_range_on(ctx) || (ctx->p.flags & DEPO_SOFT_TALLY) || ctx->N <= 0) return;
+  launch_order<Real>(state<Real>(ctx), order_scratch<Real>(ctx), (int)ctx->N, ctx->n_cells, ctx->order_every, s);
+}
+
 template <class Real> void enqueue_step(depo_ctx *ctx, hipStream_t s) {
   const State<Real> &st = state<Real>(ctx);
+  enqueue_order<Real>(ctx, s);
   launch_prepare<Real>(st, ctx->ph, prepare_mode(ctx) | P_KICK_DRIFT, s);
   enqueue_forces<Real>(ctx, s);
   launch_finish<Real>(st, ctx->ph, F_KICK, s);
@@ -401,6 +433,7 @@ template <class Real> void enqueue_step(depo_ctx *ctx, hipStream_t s) {
 template <class Real> hipError_t capture_forked_step(depo_ctx *ctx) {
   const State<Real> &st = state<Real>(ctx);
   hipStream_t a = ctx->cap_stream, b = ctx->cap_side;
+  enqueue_order<Real>(ctx, a);
   launch_prepare<Real>(st, ctx->ph, prepare_mode(ctx) | P_KICK_DRIFT, a);
   hipError_t e = hipEventRecord(ctx->ev_fork, a);
   if (e == hipSuccess) e = hipStreamWaitEvent(b, ctx->ev_fork, 0);
@@ -465,6 +498,8 @@ template <class Real> depo_status run_steps_timed(depo_ctx *ctx, int n, hipStrea
   for (int k = 0; k < n; ++k) {
     hipEvent_t *E = &ev[6 * (size_t)k];
     HIP_TRY(hipEventRecord(E[0], s));
+    // a storage reorder counts with the particle update before the forces
+    enqueue_order<Real>(ctx, s);
     launch_prepare<Real>(st, ctx->ph, prepare_mode(ctx) | P_KICK_DRIFT, s);
     HIP_TRY(hipEventRecord(E[1], s));
     if (short_range_on(ctx)) launch_cells<Real>(st, ctx->ph, ctx->n_cells, (ctx->n_cells + 1023) / 1024, s);
@@ -660,6 +695,12 @@ depo_status do_seed(depo_ctx *ctx, const depo_sample_params *sp, const double *h
   HIP_TRY(hipMemcpyAsync(st.qb, hq, nb * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(st.ell, zeros_d.data(), nb * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(st.dep, zeros_i.data(), nb * 4, hipMemcpyHostToDevice, s));
+  {
+    std::vector<int32_t> iota(nb);
+    for (size_t i = 0; i < nb; ++i) iota[i] = (int32_t)i;
+    HIP_TRY(hipMemcpyAsync(st.perm, iota.data(), nb * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
   std::vector<Real> vbuf;
   if (hv) {
     vbuf.resize(nb);
@@ -692,6 +733,7 @@ template <class Real> depo_status check_err(depo_ctx *ctx, hipStream_t s) {
   HIP_TRY(hipMemcpyAsync(&e, state<Real>(ctx).err, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (e & ERR_NONFINITE) return ctx->fail(DEPO_E_NONFINITE, "a velocity or acceleration became non-finite");
+  if (e & ERR_ORDER) return ctx->fail(DEPO_E_CORRUPT, "storage reorder met a cell list that does not match the state");
   return DEPO_OK;
 }
 
@@ -700,6 +742,12 @@ depo_status do_read(depo_ctx *ctx, double *hx, double *hv, double *ha, int32_t *
   using Pos = typename Prec<Real>::Pos;
   const State<Real> &st = state<Real>(ctx);
   const size_t N = (size_t)ctx->N;
+  // slot k holds particle perm[k] of the caller's order
+  std::vector<int32_t> perm(N);
+  if (N) HIP_TRY(hipMemcpyAsync(perm.data(), st.perm, N * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (size_t k = 0; k < N; ++k)
+    if (perm[k] < 0 || (size_t)perm[k] >= N) return ctx->fail(DEPO_E_CORRUPT, "particle permutation corrupted");
   if (hx) {
     std::vector<Pos> p(3 * N);
     std::vector<Real> r(3 * N);
@@ -714,13 +762,14 @@ depo_status do_read(depo_ctx *ctx, double *hx, double *hv, double *ha, int32_t *
       double x = ((double)p[i] + (double)r[i]) * ctx->ph.ux;
       if (x < 0.0) x += ctx->p.L;
       if (x >= ctx->p.L) x -= ctx->p.L;
-      hx[3 * i] = x;
+      double *o = hx + 3 * (size_t)perm[i];
+      o[0] = x;
       if constexpr (sizeof(Pos) == 4) {
-        hx[3 * i + 1] = ((double)(int32_t)p[N + i] + (double)r[N + i]) * ctx->ph.ur;
-        hx[3 * i + 2] = ((double)(int32_t)p[2 * N + i] + (double)r[2 * N + i]) * ctx->ph.ur;
+        o[1] = ((double)(int32_t)p[N + i] + (double)r[N + i]) * ctx->ph.ur;
+        o[2] = ((double)(int32_t)p[2 * N + i] + (double)r[2 * N + i]) * ctx->ph.ur;
       } else {
-        hx[3 * i + 1] = ((double)(int64_t)p[N + i] + (double)r[N + i]) * ctx->ph.ur;
-        hx[3 * i + 2] = ((double)(int64_t)p[2 * N + i] + (double)r[2 * N + i]) * ctx->ph.ur;
+        o[1] = ((double)(int64_t)p[N + i] + (double)r[N + i]) * ctx->ph.ur;
+        o[2] = ((double)(int64_t)p[2 * N + i] + (double)r[2 * N + i]) * ctx->ph.ur;
       }
     }
   }
@@ -731,15 +780,21 @@ depo_status do_read(depo_ctx *ctx, double *hx, double *hv, double *ha, int32_t *
     HIP_TRY(hipMemcpyAsync(t.data() + 2 * N, c, N * sizeof(Real), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     for (size_t i = 0; i < N; ++i)
-      for (int k = 0; k < 3; ++k) h[3 * i + k] = (double)t[k * N + i];
+      for (int k = 0; k < 3; ++k) h[3 * (size_t)perm[i] + k] = (double)t[k * N + i];
+    return DEPO_OK;
+  };
+  auto ints = [&](int32_t *h, const int32_t *a) -> depo_status {
+    std::vector<int32_t> t(N);
+    if (N) HIP_TRY(hipMemcpyAsync(t.data(), a, N * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (size_t i = 0; i < N; ++i) h[perm[i]] = t[i];
     return DEPO_OK;
   };
   depo_status r;
   if (hv && (r = vec3(hv, st.vx, st.vy, st.vz)) != DEPO_OK) return r;
   if (ha && (r = vec3(ha, st.ax, st.ay, st.az)) != DEPO_OK) return r;
-  if (hdep) HIP_TRY(hipMemcpyAsync(hdep, st.dep, N * 4, hipMemcpyDeviceToHost, s));
-  if (hnb) HIP_TRY(hipMemcpyAsync(hnb, st.nbr, N * 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  if (hdep && (r = ints(hdep, st.dep)) != DEPO_OK) return r;
+  if (hnb && (r = ints(hnb, st.nbr)) != DEPO_OK) return r;
   return check_err<Real>(ctx, s);
 }
 
@@ -771,10 +826,11 @@ template <class Real> depo_status do_tally(depo_ctx *ctx, depo_tally *out, hipSt
 
 // checkpoint payload: positions (fixed point, then remainders), velocities, accelerations,
 // fluid velocities, d, qbase, ell, dep, per-sample parameters
-constexpr uint32_t kBlobVersion = 2;
+// (all in storage order), then the storage permutation
+constexpr uint32_t kBlobVersion = 3;
 template <class Real> size_t blob_payload(const depo_ctx *ctx) {
   const size_t N = (size_t)ctx->N;
-  return N * (3 * sizeof(typename Prec<Real>::Pos) + 12 * sizeof(Real) + 3 * 8 + 4) +
+  return N * (3 * sizeof(typename Prec<Real>::Pos) + 12 * sizeof(Real) + 3 * 8 + 4 + 4) +
          (size_t)ctx->S * sizeof(depo_sample_params);
 }
 
@@ -798,6 +854,7 @@ template <class Real> depo_status do_download(depo_ctx *ctx, void *blob, size_t 
   for (const double *a : {st.d, st.qb, st.ell})
     if ((r = get(a, N * 8)) != DEPO_OK) return r;
   if ((r = get(st.dep, N * 4)) != DEPO_OK) return r;
+  if ((r = get(st.perm, N * 4)) != DEPO_OK) return r;
   HIP_TRY(hipStreamSynchronize(s));
   std::memcpy(p, ctx->sp.data(), ctx->S * sizeof(depo_sample_params));
   BlobHeader h{};
@@ -826,6 +883,17 @@ template <class Real> depo_status do_upload(depo_ctx *ctx, const void *blob, siz
     return ctx->fail(DEPO_E_CORRUPT, "blob header does not match this context");
   const char *p = (const char *)blob + sizeof(BlobHeader);
   if (crc32_update(0, p, pay) != h.crc) return ctx->fail(DEPO_E_CORRUPT, "blob CRC mismatch");
+  {
+    // the storage permutation must be one (it indexes the host arrays of depo_read_particles)
+    std::vector<int32_t> perm(N);
+    std::memcpy(perm.data(), p + N * (3 * sizeof(Pos) + 12 * sizeof(Real) + 3 * 8 + 4), N * 4);
+    std::vector<char> seen(N, 0);
+    for (size_t k = 0; k < N; ++k) {
+      if (perm[k] < 0 || (size_t)perm[k] >= N || seen[perm[k]])
+        return ctx->fail(DEPO_E_CORRUPT, "blob permutation invalid");
+      seen[perm[k]] = 1;
+    }
+  }
   // per-sample parameters and diameters rebuild the sample table
   const char *q = p + N * (3 * sizeof(Pos) + 12 * sizeof(Real));
   std::vector<double> d(N);
@@ -853,13 +921,15 @@ template <class Real> depo_status do_upload(depo_ctx *ctx, const void *blob, siz
   for (double *a : {st.d, st.qb, st.ell})
     if ((r = put(a, N * 8)) != DEPO_OK) return r;
   if ((r = put(st.dep, N * 4)) != DEPO_OK) return r;
+  if ((r = put(st.perm, N * 4)) != DEPO_OK) return r;
   const int32_t ns = h.nstep;
   HIP_TRY(hipMemcpyAsync(st.nstep, &ns, 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
   // the tables a context that was never seeded lacks (sample ids, pair-kernel work lists, ...)
   if ((r = upload_tables<Real>(ctx, s)) != DEPO_OK) return r;
-  // refresh the Coulomb source radii
-  launch_prepare<Real>(st, ctx->ph, P_SEED | P_COULOMB, s);
+  // refresh the Coulomb source radii and the cell list (a storage reorder reads it)
+  launch_prepare<Real>(st, ctx->ph, P_SEED | P_COULOMB | (short_range_on(ctx) ? P_CELLS : 0), s);
+  if (short_range_on(ctx)) launch_cells<Real>(st, ctx->ph, ctx->n_cells, (ctx->n_cells + 1023) / 1024, s);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   ctx->nstep = h.nstep;
@@ -1467,6 +1537,15 @@ depo_status depo_adjoint_noalloc(depo_ctx *ctx, int32_t n_steps, int32_t ckpt_ev
   ctx->use_graph = graph;
   if (r != DEPO_OK) return r;
   return depo_adjoint_backward(ctx, h_weights, h_grad, stream);
+}
+
+depo_status depo_set_reorder(depo_ctx *ctx, int32_t every) {
+  if (!ctx) return DEPO_E_INVALID;
+  ++ctx->gen;   // a pending adjoint reverse sweep no longer applies
+  if (every < 0 || every > (1 << 20)) return ctx->fail(DEPO_E_INVALID, "reorder interval must be 0..2^20 steps");
+  ctx->order_every = every;
+  ctx->drop_graph();
+  return DEPO_OK;
 }
 
 static bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }

@@ -14,6 +14,11 @@ template <class Real> void launch_prepare(const State<Real> &st, const Phys &ph,
 template <class Real> void launch_finish(const State<Real> &st, const Phys &ph, int mode, hipStream_t s);
 template <class Real> void launch_tally(const State<Real> &st, const Phys &ph, int nstep, hipStream_t s);
 
+// Storage order: at the start of a step that follows a multiple of `every` steps (decided on the
+// device from the step counter), permute the per-particle state into the order of the last cell list.
+template <class Real>
+void launch_order(const State<Real> &st, const OrderScratch<Real> &sc, int n, int n_cells, int every, hipStream_t s);
+
 // Cell list: scan of the histogram, scatter, in-cell ordering, short-range forces.
 template <class Real>
 void launch_cells(const State<Real> &st, const Phys &ph, int n_cells, int n_scan_blocks, hipStream_t s);

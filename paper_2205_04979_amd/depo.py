@@ -91,6 +91,7 @@ _SIGS = {
     "depo_adjoint_backward": (C.c_int, [_P, _DP, _DP, _P]),
     "depo_adjoint_noalloc": (C.c_int, [_P, C.c_int32, C.c_int32, _DP, _DP, _P]),
     "depo_set_p3m": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_double, C.c_double]),
+    "depo_set_reorder": (C.c_int, [_P, C.c_int32]),
     "depo_lf_solve": (C.c_int, [C.POINTER(Params), C.c_int64, _P, _P, _P, C.c_int32, C.c_int32, _P, _P]),
 }
 
@@ -269,6 +270,10 @@ class Simulation(Context):
                 PAIR_KAHAN if self.real_bytes == 4 else PAIR_PLAIN)
         self.check(self._L.depo_set_kernel_config(self._h, targets_per_lane, waves, block, int(mode),
                                                   int(use_graph)), "depo_set_kernel_config")
+
+    def set_reorder(self, every: int):
+        """Steps between storage reorders into cell order (0: never, the library default)."""
+        self.check(self._L.depo_set_reorder(self._h, int(every)), "depo_set_reorder")
 
     def step(self, n: int = 1, stream=None):
         self.check(self._L.depo_step(self._h, int(n), self._stream(stream)), "depo_step")

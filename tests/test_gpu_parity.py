@@ -12,6 +12,7 @@ import sys
 import numpy as np
 import pytest
 
+from oracle.sim import OracleSim
 from synthetic import make_workload
 from synthetic.workloads import physical_params
 from tests.gpu_common import (coulomb_scale, force_error, near_wall_particles, oracle_from_snapshot,
@@ -207,13 +208,15 @@ def test_short_range_pairs_at_and_near_saturation_per_particle(real_bytes):
     a small overlap through the saturation gap delta_M = delta_min (k_r/k)^(1/4) up to near the d/4
     cutoff, unequal and equal diameters, small relative velocities: every particle's acceleration is its
     one pair force, compared with the oracle per particle relative to |a| alone.  FP64: 1e-12; FP32: 5e-6
-    (the gap is formed in FP64 from the fixed-point differences, the force in FP32)."""
+    (the gap is formed in FP64 from the fixed-point differences, the force in FP32); plus, for pairs in
+    contact, what the double-precision input positions alone can move a contact force."""
     from oracle.physics import vdw_saturation_gap
     rng = np.random.default_rng(41)
     p = physical_params(180.0, drag=False, coulomb=False, wall_image=False, wall_vdw=False)
     R, L = p["R"], p["L"]
     dm = vdw_saturation_gap(p)
-    factors = np.array([-40.0, -0.5, 0.0, 0.2, 0.9, 0.999, 1.001, 1.1, 3.0, 30.0, 100.0, 200.0])
+    # touching pairs are left out: at gap 0 the contact damping switches on or off with the last bit
+    factors = np.array([-40.0, -0.5, -1e-3, 1e-3, 0.2, 0.9, 0.999, 1.001, 1.1, 3.0, 30.0, 100.0, 200.0])
     n_pairs = 96
     centres = []
     while len(centres) < n_pairs:     # pair centres at least 0.3 mm apart, inside |y|, |z| < R/2
@@ -245,7 +248,14 @@ def test_short_range_pairs_at_and_near_saturation_per_particle(real_bytes):
     worst = int(np.argmax(e))
     say(f"per particle: max {e.max():.3e} (pair {worst // 2}, gap / delta_M {factors[(worst // 2) % factors.size]}) "
         f"median {np.median(e):.3e}")
-    assert e.max() < (1e-12 if real_bytes == 8 else 5e-6)
+    # the positions reach both sides as doubles (spacing 1.7e-18 m at |y| = 1 cm; the FP64 form holds
+    # them to 2.2e-21 m): at the contact stiffness K (tau_col = 15 dt) a contact force may differ by
+    # K * 4e-18 m from that alone
+    tau = p["tau_col_steps"] * p["dt"]
+    k_contact = (np.pi ** 2 + np.log(p["e_pp"]) ** 2) / tau ** 2
+    bound = (1e-12 if real_bytes == 8 else 5e-6) + k_contact * 4e-18 / an
+    say("largest error / bound", float(np.max(e / bound)))
+    assert np.all(e <= bound)
 
 
 def test_fp64_batched_samples_with_rebound():
@@ -484,6 +494,7 @@ def test_checkpoint_restores_into_a_fresh_context_on_a_dirty_workspace(p3m):
     cfg = dict(mesh_x=32, mesh_yz=16, alpha_h=0.5, rmax_alpha=3.5) if p3m else None
     say("case: checkpoint into a fresh context on a dirty workspace, p3m =", p3m)
     src = Simulation(w.params, w.offsets, f.shape[:3], real_bytes=4, p3m=cfg)
+    src.set_reorder(4)
     src.init_field(f)
     src.seed(w.sample_params, w.x, w.d, w.qbase)
     src.step(5)
@@ -495,6 +506,7 @@ def test_checkpoint_restores_into_a_fresh_context_on_a_dirty_workspace(p3m):
     torch.cuda.synchronize()
     del dirty
     dst = Simulation(w.params, w.offsets, f.shape[:3], real_bytes=4, p3m=cfg)
+    dst.set_reorder(4)
     if not (lo <= dst._ws.data_ptr() < hi):
         pytest.skip("the caching allocator did not hand back the dirtied block")
     dst.init_field(f)
@@ -519,12 +531,47 @@ def test_graph_replay_equals_direct_launch(cfg):
     for graph in (True, False):
         sim, _ = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4, oracle=False)
         sim.set_kernel_config(*cfg, use_graph=graph)
+        sim.set_reorder(5)        # storage reorders at 5 and 10 steps, between and inside the replays
         for _ in range(3):
             sim.step(4)
             out_k = sim.read()   # eager synchronisation between replays
         out.append(out_k)
     for k in ("x", "v", "a"):
         assert np.array_equal(out[0][k], out[1][k]), k
+
+
+@pytest.mark.parametrize("real_bytes", [8, 4])
+def test_storage_reorder_keeps_the_trajectory(real_bytes):
+    """Storage reorders into cell order every 3 steps against none, on a workload with removals (the
+    depositing 1,024-particle variant, 60 steps) and on batched samples of uneven size with the rebound
+    law: every particle, returned in the caller's order, at the same place (FP64: 1e-13 R; FP32: 1e-6 R,
+    the sums that follow the storage order round differently), identical deposition steps and per-sample
+    counts; the FP64 form also against the oracle."""
+    cases = [make_workload("plain-1k-dep"),
+             make_workload("batched-256", n_samples=5, n_lo=60, n_hi=400, field_n=32)]
+    for w in cases:
+        f = w.field()
+        say("case: storage reorder,", w.name, "fp", 8 * real_bytes)
+        runs = {}
+        for every in (0, 3):
+            sim, _ = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, real_bytes, oracle=False)
+            sim.set_reorder(every)
+            sim.step(60)
+            runs[every] = (sim.read(), sim.tally())
+        (a, ta), (b, tb) = runs[0], runs[3]
+        assert np.array_equal(a["dep_step"], b["dep_step"])
+        assert [t["n_dep"] for t in ta] == [t["n_dep"] for t in tb]
+        both = a["dep_step"] == 0
+        err = position_error(b["x"][both], a["x"][both], w.params["L"], w.params["R"])
+        say("reordered vs fixed order: max |dx|/R", err.max(), "deposited", int((a["dep_step"] > 0).sum()))
+        assert err.max() < (1e-13 if real_bytes == 8 else 1e-6)
+        assert np.array_equal(a["neighbours"] >= 0, b["neighbours"] >= 0)
+        if real_bytes == 8:
+            ora = OracleSim(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params)
+            ora.step(60)
+            assert np.array_equal(b["dep_step"], ora.dep_step)
+            al = ora.alive
+            assert position_error(b["x"][al], ora.x[al], ora.L, ora.R).max() < 1e-12
 
 
 @pytest.mark.parametrize("cfg", [(1, 4, 32), (2, 8, 32), (4, 4, 32), (2, 16, 32), (1, 16, 64), (2, 8, 64),
