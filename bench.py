@@ -506,6 +506,8 @@ def main():
     ap.add_argument("--reorder", type=int, default=REORDER,
                     help="steps between storage reorders into cell order in the batched, large and p3m legs "
                          "(0: none); set after the autotuner has run")
+    ap.add_argument("--single-reorder", type=int, default=0,
+                    help="steps between storage reorders in the headline leg (0: none, the library default)")
     ap.add_argument("--clock-warmup-ms", type=float, default=200.0,
                     help="GPU busy time (matrix products, not steps) right before the warm-up steps")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -589,6 +591,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.single_reorder:
+        sim.set_reorder(args.single_reorder)
     if args.clock_warmup_ms > 0:
         # keep the GPU busy (plain matrix products, no simulation state touched) until the clocks have
         # ramped up, so that a short timed region does not measure the ramp
@@ -648,7 +652,8 @@ def main():
                    "alive_at_end": int(n_alive), "pair_kernel_shape": list(shape),
                    "autotune_ms_per_step": None if tune is None else {",".join(map(str, k)): round(v, 4) for k, v in tune.items()}, "ms_per_step_direct_launch_with_events": round(1e3 * wall_phases / p_steps, 5),
                    "phase_ms_per_step": {k: round(v / p_steps, 5) for k, v in phase_ms.items()},
-                   "phase_steps": p_steps, "clock_warmup_ms": args.clock_warmup_ms},
+                   "phase_steps": p_steps, "clock_warmup_ms": args.clock_warmup_ms,
+                   "reorder_every": args.single_reorder},
         "roofline": roofline,
     }
     if args.secondary_steps > 0 and args.workload == "single-65k":

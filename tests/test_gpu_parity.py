@@ -558,6 +558,16 @@ def test_storage_reorder_keeps_the_trajectory(real_bytes):
             sim.set_reorder(every)
             sim.step(60)
             runs[every] = (sim.read(), sim.tally())
+            # the storage permutation, as the checkpoint blob carries it (after a 48-byte header: positions,
+            # 12 per-particle reals, 3 doubles and the deposition step, then the permutation)
+            n = w.n_particles
+            off = 48 + n * (3 * real_bytes + 12 * real_bytes + 3 * 8 + 4)
+            perm = np.frombuffer(sim.state_download(), dtype=np.int32, count=n, offset=off)
+            assert np.array_equal(np.sort(perm), np.arange(n))
+            assert np.array_equal(perm, np.arange(n)) == (every == 0), "reordered storage expected"
+            for s in range(w.n_samples):   # every sample keeps its slots
+                sl = slice(w.offsets[s], w.offsets[s + 1])
+                assert np.all((perm[sl] >= w.offsets[s]) & (perm[sl] < w.offsets[s + 1]))
         (a, ta), (b, tb) = runs[0], runs[3]
         assert np.array_equal(a["dep_step"], b["dep_step"])
         assert [t["n_dep"] for t in ta] == [t["n_dep"] for t in tb]
