@@ -410,8 +410,9 @@ __device__ __forceinline__ int3 sr_cell(const State<Real> &st, const Phys &ph, c
   return make_int3(cx, cy, cz);
 }
 
-// Cell id and octant of the particle within it (4 hx + 2 hy + hz, from the cell's halves along
-// each axis), packed as 8 id + octant.
+// Cell id and sub-cell key of the particle, packed as 64 id + key.  The key orders the 4 x 4 x 4
+// sub-cells of a cell along a Morton curve (bits: the halves along x, y, z, then the quarters
+// within them), so that consecutive particles of the cell-sorted order lie close together.
 template <class Real>
 __global__ void k_p3m_bin(State<Real> st, Phys ph, P3mDev m, int32_t *__restrict__ cell_of,
                           int32_t *__restrict__ counts) {
@@ -423,9 +424,11 @@ __global__ void k_p3m_bin(State<Real> st, Phys ph, P3mDev m, int32_t *__restrict
   const double x = ((double)st.px[i] + (double)st.rx[i]) * ph.ux;
   const double y = ((double)(SPos)st.py[i] + (double)st.ry[i]) * ph.ur;
   const double z = ((double)(SPos)st.pz[i] + (double)st.rz[i]) * ph.ur;
-  const int hx = (x / ph.L * m.ncx - c.x) >= 0.5, hy = ((y + ph.R) / (2.0 * ph.R) * m.ncy - c.y) >= 0.5,
-            hz = ((z + ph.R) / (2.0 * ph.R) * m.ncy - c.z) >= 0.5;
-  cell_of[i] = 8 * id + 4 * hx + 2 * hy + hz;
+  auto quarter = [](double f) { return min(max((int)(4.0 * f), 0), 3); };
+  const int qx = quarter(x / ph.L * m.ncx - c.x), qy = quarter((y + ph.R) / (2.0 * ph.R) * m.ncy - c.y),
+            qz = quarter((z + ph.R) / (2.0 * ph.R) * m.ncy - c.z);
+  const int key = ((qx >> 1) << 5) | ((qy >> 1) << 4) | ((qz >> 1) << 3) | ((qx & 1) << 2) | ((qy & 1) << 1) | (qz & 1);
+  cell_of[i] = 64 * id + key;
   atomicAdd(counts + id, 1);
 }
 
@@ -459,12 +462,12 @@ __global__ void k_p3m_scatter(int32_t N, const int32_t *__restrict__ cell_of, in
                               int32_t *__restrict__ sorted) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  sorted[atomicAdd(fill + (cell_of[i] >> 3), 1)] = i;
+  sorted[atomicAdd(fill + (cell_of[i] >> 6), 1)] = i;
 }
 
-// Particles of each cell ordered by (octant, index): a fixed summation order in which
+// Particles of each cell ordered by (sub-cell key, index): a fixed summation order in which
 // consecutive targets of the short-range pass are close together.  The counts are cleared.  One
-// workgroup per cell: the cell's keys (octant, index; distinct) are staged in LDS and each
+// workgroup per cell: the cell's keys (sub-cell key, index; distinct) are staged in LDS and each
 // particle is written to its rank (the number of smaller keys).  A cell of more than kSortCap
 // particles is sorted by one thread.
 constexpr int kSortCap = 2048;
@@ -474,7 +477,7 @@ __global__ __launch_bounds__(256) void k_p3m_sort(int32_t ncell, const int32_t *
   __shared__ int64_t v[kSortCap];
   const int c = blockIdx.x;
   const int b = starts[c], n = starts[c + 1] - b;
-  auto key = [&](int i) { return ((int64_t)(cell_of[i] & 7) << 32) | (int64_t)i; };
+  auto key = [&](int i) { return ((int64_t)(cell_of[i] & 63) << 32) | (int64_t)i; };
   if (threadIdx.x == 0) counts[c] = 0;
   if (n <= 1) return;   // uniform
   if (n > kSortCap) {
@@ -502,46 +505,56 @@ __global__ __launch_bounds__(256) void k_p3m_sort(int32_t ncell, const int32_t *
   }
 }
 
-// Source record of the short-range pass, in cell-sorted order.
-template <class Real> struct __align__(sizeof(typename Prec<Real>::Pos) == 4 ? 4 : 8) SrRec {
-  typename Prec<Real>::Pos x, y, z;
-  Real q, d;
+// Source record of the short-range pass in the FP64 form, in cell-sorted order.
+struct __align__(8) SrRec64 {
+  uint64_t x;        // fixed-point position: x as the unsigned fraction of L,
+  int64_t y, z;      // y and z as signed multiples of the y/z quantum
+  double q, d;       // scaled charge, diameter [m]
 };
 
 // Cell-sorted copy of the records the short-range pass reads (contiguous per cell).
+// FP64 form: one SrRec64 per particle.  FP32 form: a 16-byte record (x bits; y and z as floats in
+// y/z position quanta, so that the short-range body takes their differences with one subtraction;
+// scaled charge) read by every pair with one LDS load, and the radius in y/z position quanta in an
+// array of its own, read only for pairs that may overlap; both arrays share the record region
+// (16 N bytes, then 4 N).
 template <class Real>
-__global__ void k_p3m_records(State<Real> st, Phys ph, const int32_t *__restrict__ sorted, SrRec<Real> *rec) {
+__global__ void k_p3m_records(State<Real> st, Phys ph, const int32_t *__restrict__ sorted, void *rec) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= ph.N) return;
   const int i = sorted[k];
-  SrRec<Real> r;
-  r.x = st.px[i];
+  using SPos = typename std::make_signed<typename Prec<Real>::Pos>::type;
   if constexpr (sizeof(Real) == 4) {
-    // FP32 form: y and z as floats in y/z position quanta (bit patterns in the Pos fields), so that
-    // the short-range body takes their differences with one subtraction
-    using SPos = typename std::make_signed<typename Prec<Real>::Pos>::type;
-    r.y = __float_as_uint((float)((double)(SPos)st.py[i] + (double)st.ry[i]));
-    r.z = __float_as_uint((float)((double)(SPos)st.pz[i] + (double)st.rz[i]));
+    float4 r;
+    r.x = __uint_as_float(st.px[i]);
+    r.y = (float)((double)(SPos)st.py[i] + (double)st.ry[i]);
+    r.z = (float)((double)(SPos)st.pz[i] + (double)st.rz[i]);
+    r.w = st.js[i].q;
+    ((float4 *)rec)[k] = r;
+    ((float *)((float4 *)rec + ph.N))[k] = (float)(0.5 * st.d[i] * ph.inv_ur);
   } else {
-    r.y = st.py[i];
-    r.z = st.pz[i];
+    SrRec64 r;
+    r.x = st.px[i];
+    r.y = (SPos)st.py[i];
+    r.z = (SPos)st.pz[i];
+    r.q = st.js[i].q;
+    r.d = st.d[i];
+    ((SrRec64 *)rec)[k] = r;
   }
-  r.q = st.js[i].q;
-  // FP32: the radius in y/z position quanta (the short-range body works in those units);
-  // FP64: the diameter in metres
-  r.d = sizeof(Real) == 4 ? Real(0.5 * st.d[i] * ph.inv_ur) : Real(st.d[i]);
-  rec[k] = r;
 }
 
 constexpr int kSrLds = 65536;    // bytes of LDS for staged neighbour records (FP64 form)
-// the same for the FP32 form, which also holds the profile table: 28,000 B of records + 16.4 KB
-// of table + 6 KB of partial sums keep a workgroup within a third of the 160 KB LDS, so three
-// workgroups (24 waves) share a CU
-constexpr int kSrLdsF32 = 28000;
 constexpr int kSrWaves = 8;      // waves per cell
 constexpr int kSrLanes = 64 * kSrWaves;
-constexpr int kSrMaxSlices = 32; // at most this many threads share one target
+constexpr int kSrMaxSlices = 32; // FP64 form: at most this many threads share one target
 constexpr int kSrTable = 2048;   // intervals of the tabulated short-range profile (FP32 form)
+// FP32 form: 28,000 B of staged records + 16.4 KB of table + 7 KB of source lists keep a workgroup
+// within a third of the 160 KB LDS, so three workgroups (24 waves) share a CU
+constexpr int kSrLdsF32 = 28000;
+constexpr int kSrCluster = 8;                     // FP32 form: targets of one wave (a cluster)
+constexpr int kSrSlices = 64 / kSrCluster;        // lanes per target
+constexpr int kSrRounds = 64;                     // clusters per wave and staging pass
+constexpr int kSrList = 448;                      // entries of a wave's source list
 
 // Short-range force profile g(s) = erfc(s) + (2 s / sqrt(pi)) exp(-s^2), s = alpha r, so that the
 // short-range force of a non-overlapping pair is q g(alpha r) r_vec / r^3; tabulated on
@@ -560,36 +573,11 @@ __global__ void k_p3m_table(P3mDev m, float2 *__restrict__ tab) {
   tab[k] = make_float2((float)g0, (float)(g1 - g0));
 }
 
-// Short range (Coulomb with the overlap clamp minus the erf field) over nearest-image neighbours
-// closer than r_max, added to the long-range part; result in units of the x quantum.  One
-// workgroup per cell: the records of the 27 neighbouring cells are staged in LDS (in chunks when
-// they exceed it); the cell's nb targets (up to 512 at a time) share the 512 threads, S =
-// 512 / nb threads per target (at most 32), and thread g takes target g mod nb and every S-th
-// staged source from slice g / nb on; the S partial sums of a target are combined in FP64 in
-// slice order.  FP32: branch-free tabulated profile read from
-// a copy of the table in LDS, in y/z position quanta (overlapping pairs, which are rare, take the
-// exact clamp); FP64: the exact expressions, in metres.
-template <class Real>
-__global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phys ph, P3mDev m,
-                                                             const int32_t *__restrict__ starts,
-                                                             const int32_t *__restrict__ sorted,
-                                                             const SrRec<Real> *__restrict__ rec,
-                                                             const double *__restrict__ slong,
-                                                             const float2 *__restrict__ tab) {
-  using Pos = typename Prec<Real>::Pos;
-  using SPos = typename std::make_signed<Pos>::type;
-  // FP32: 28 KB of staged records + the 16 KB profile table in LDS (three workgroups per CU)
-  constexpr int CAP = (sizeof(Real) == 4 ? kSrLdsF32 : kSrLds) / sizeof(SrRec<Real>);
-  __shared__ SrRec<Real> src[CAP];
-  __shared__ float2 stab[sizeof(Real) == 4 ? kSrTable + 1 : 1];
-  __shared__ Real part[3][kSrLanes];
-  __shared__ int32_t rb[27], rn[27], roff[28];
-  const int c = blockIdx.x;
-  const int cz = c % m.ncy, cy = (c / m.ncy) % m.ncy, cx = c / (m.ncy * m.ncy);
-  const int t0 = starts[c], nt = starts[c + 1] - t0;
-  if (nt == 0) return;   // uniform: the whole workgroup leaves
-  if constexpr (sizeof(Real) == 4)   // read after the barriers below
-    for (int k = threadIdx.x; k <= kSrTable; k += 64 * kSrWaves) stab[k] = tab[k];
+// The 27 cells around cell c (periodic in x; none beyond the section) as ranges of the
+// cell-sorted records: begin rb, count rn and offset roff in their concatenation (roff[27] is the
+// total).  Called by every thread; returns after a barrier.
+__device__ __forceinline__ void neighbour_ranges(const P3mDev &m, const int32_t *__restrict__ starts, int cx,
+                                                 int cy, int cz, int32_t *rb, int32_t *rn, int32_t *roff) {
   if (threadIdx.x < 27) {
     const int ox = (int)threadIdx.x / 9 - 1, oy = ((int)threadIdx.x / 3) % 3 - 1, oz = (int)threadIdx.x % 3 - 1;
     int x = cx + ox;
@@ -610,17 +598,50 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
     for (int k = 0; k < 27; ++k) roff[k + 1] = roff[k] + rn[k];
   }
   __syncthreads();
+}
+
+// Stage entries [cb, cb + n) of the concatenated 27 cell ranges into LDS, cell by cell (and,
+// when rad is given, the radii beside them).
+template <class Rec>
+__device__ __forceinline__ void stage_sources(const Rec *__restrict__ rec, const float *__restrict__ rad,
+                                              const int32_t *rb, const int32_t *roff, int cb, int n, Rec *src,
+                                              float *srad) {
+  __syncthreads();
+  for (int k = 0; k < 27; ++k) {
+    const int lo = max(roff[k], cb), hi = min(roff[k + 1], cb + n);
+    for (int q = lo + (int)threadIdx.x; q < hi; q += blockDim.x) {
+      src[q - cb] = rec[rb[k] + (q - roff[k])];
+      if (rad) srad[q - cb] = rad[rb[k] + (q - roff[k])];
+    }
+  }
+  __syncthreads();
+}
+
+// Short range (Coulomb with the overlap clamp minus the erf field) over nearest-image neighbours
+// closer than r_max, added to the long-range part; result in units of the x quantum.
+//
+// FP64 form: the exact expressions, in metres.  One workgroup per cell: the records of the 27
+// neighbouring cells are staged in LDS (in chunks when they exceed it); the cell's nb targets (up
+// to 512 at a time) share the 512 threads, S = 512 / nb threads per target (at most 32), and
+// thread g takes target g mod nb and every S-th staged source from slice g / nb on; the S partial
+// sums of a target are combined in FP64 in slice order.
+__global__ __launch_bounds__(kSrLanes) void k_p3m_short_f64(State<double> st, Phys ph, P3mDev m,
+                                                            const int32_t *__restrict__ starts,
+                                                            const int32_t *__restrict__ sorted,
+                                                            const SrRec64 *__restrict__ rec,
+                                                            const double *__restrict__ slong) {
+  constexpr int CAP = kSrLds / sizeof(SrRec64);
+  __shared__ SrRec64 src[CAP];
+  __shared__ double part[3][kSrLanes];
+  __shared__ int32_t rb[27], rn[27], roff[28];
+  const int c = blockIdx.x;
+  const int cz = c % m.ncy, cy = (c / m.ncy) % m.ncy, cx = c / (m.ncy * m.ncy);
+  const int t0 = starts[c], nt = starts[c + 1] - t0;
+  if (nt == 0) return;   // uniform: the whole workgroup leaves
+  neighbour_ranges(m, starts, cx, cy, cz, rb, rn, roff);
   const int total = roff[27];
-  const Real ux = Real(ph.ux), ur = Real(ph.ur);
-  const Real a = Real(m.alpha), c2 = Real(2.0 * m.alpha / sqrt(M_PI)), rmax2 = Real(m.rmax * m.rmax);
-  // FP32 form, in y/z position quanta: x differences scaled by u_x / u_r, alpha per quantum,
-  // table coordinate u = r * tq, the largest contact distance squared
-  const float kx = (float)(ph.ux / ph.ur), aq = (float)(m.alpha * ph.ur), c2q = (float)(2.0 * m.alpha * ph.ur / sqrt(M_PI));
-  const float tq = (float)(kSrTable * ph.ur / m.rmax);
-  const float near2q = (float)(ph.near2 * (ph.ux / ph.ur) * (ph.ux / ph.ur));
-  // beyond this (r_max squared in quanta, plus 1e-4 for rounding) the table coordinate u is
-  // surely past the last interval, so the pair adds an exact zero
-  const float skip2q = (float)((m.rmax / ph.ur) * (m.rmax / ph.ur) * 1.0001);
+  const double ux = ph.ux, ur = ph.ur;
+  const double a = m.alpha, c2 = 2.0 * m.alpha / sqrt(M_PI), rmax2 = m.rmax * m.rmax;
   const bool once = total <= CAP;   // all sources fit: staged once for every target block
   for (int tb = 0; tb < nt; tb += kSrLanes) {
     const int nb = min(kSrLanes, nt - tb);
@@ -628,63 +649,28 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
     const int g = threadIdx.x;
     const bool has = g < nb * S;
     const int t = has ? g % nb : 0, slice = has ? g / nb : 0;
-    const SrRec<Real> me = rec[t0 + tb + t];
-    Real sx = 0, sy = 0, sz = 0;
+    const SrRec64 me = rec[t0 + tb + t];
+    double sx = 0, sy = 0, sz = 0;
     for (int cb = 0; cb < total; cb += CAP) {
       const int n = min(CAP, total - cb);
-      if (!once || tb == 0) {
-        __syncthreads();
-        // staged entries [cb, cb + n) of the concatenated 27 cell ranges, cell by cell
-        for (int k = 0; k < 27; ++k) {
-          const int lo = max(roff[k], cb), hi = min(roff[k + 1], cb + n);
-          for (int q = lo + (int)threadIdx.x; q < hi; q += kSrLanes) src[q - cb] = rec[rb[k] + (q - roff[k])];
-        }
-        __syncthreads();
-      }
+      if (!once || tb == 0) stage_sources(rec, (const float *)nullptr, rb, roff, cb, n, src, (float *)nullptr);
       if (!has) continue;
-#pragma unroll 4
       for (int e = slice; e < n; e += S) {
-        const SrRec<Real> s = src[e];
-        if constexpr (sizeof(Real) == 4) {
-          // y/z quanta; r2 carries 1e-20 (below the rounding of any r2 >= 1, i.e. of any two distinct
-          // positions) so that r = 0 (the target itself) gives a finite f times dx = 0
-          const float dx = (float)(int32_t)(me.x - s.x) * kx;
-          const float dy = __uint_as_float(me.y) - __uint_as_float(s.y);
-          const float dz = __uint_as_float(me.z) - __uint_as_float(s.z);
-          const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, 1e-20f)));
-          if (!__builtin_amdgcn_ballot_w64(r2 < skip2q)) continue;   // no active lane within r_max
-          const float inv = __builtin_amdgcn_rsqf(r2);
-          const float r = r2 * inv;
-          const float u = fminf(r * tq, (float)kSrTable);   // u >= kSrTable: beyond r_max, entry (0, 0)
-          const float2 tv = stab[(int)u];
-          float f = s.q * fmaf(__builtin_amdgcn_fractf(u), tv.y, tv.x) * ((inv * inv) * inv);
-          if (__builtin_amdgcn_ballot_w64(r2 < near2q)) {
-            // a pair of this source may overlap: clamped Coulomb minus the erf field, exactly
-            const float dij = me.d + s.d;
-            if (r2 > 1e-20f && r < dij) {
-              const float gg = c2q * expf(-aq * aq * r2) / r;
-              f = s.q * (1.0f / (dij * dij) - (erff(aq * r) / r2 - gg)) / r;
-            }
-          }
-          sx = fmaf(f, dx, sx);
-          sy = fmaf(f, dy, sy);
-          sz = fmaf(f, dz, sz);
-        } else {
-          const Real dx = Real((SPos)(me.x - s.x)) * ux;
-          const Real dy = Real((SPos)me.y - (SPos)s.y) * ur;
-          const Real dz = Real((SPos)me.z - (SPos)s.z) * ur;
-          const Real r2 = dx * dx + dy * dy + dz * dz;
-          const Real dij = Real(0.5) * (me.d + s.d);
-          Real f = 0.0;
-          if (r2 < rmax2 && r2 > Real(0)) {
-            const double r = sqrt(r2);
-            const double gg = c2 * exp(-a * a * r2) / r;
-            f = (r >= dij ? erfc(a * r) / r2 + gg : 1.0 / (dij * dij) - (erf(a * r) / r2 - gg)) * s.q / r;
-          }
-          sx += f * dx;
-          sy += f * dy;
-          sz += f * dz;
+        const SrRec64 s = src[e];
+        const double dx = double((int64_t)(me.x - s.x)) * ux;
+        const double dy = double(me.y - s.y) * ur;
+        const double dz = double(me.z - s.z) * ur;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double dij = 0.5 * (me.d + s.d);
+        double f = 0.0;
+        if (r2 < rmax2 && r2 > 0.0) {
+          const double r = sqrt(r2);
+          const double gg = c2 * exp(-a * a * r2) / r;
+          f = (r >= dij ? erfc(a * r) / r2 + gg : 1.0 / (dij * dij) - (erf(a * r) / r2 - gg)) * s.q / r;
         }
+        sx += f * dx;
+        sy += f * dy;
+        sz += f * dz;
       }
     }
     part[0][g] = sx;
@@ -694,19 +680,211 @@ __global__ __launch_bounds__(64 * kSrWaves) void k_p3m_short(State<Real> st, Phy
     if (g < nb) {
       double ax = 0.0, ay = 0.0, az = 0.0;
       for (int q = 0; q < S; ++q) {
-        ax += (double)part[0][q * nb + g];
-        ay += (double)part[1][q * nb + g];
-        az += (double)part[2][q * nb + g];
+        ax += part[0][q * nb + g];
+        ay += part[1][q * nb + g];
+        az += part[2][q * nb + g];
       }
       const int i = sorted[t0 + tb + g];
       const double u2 = ph.ux * ph.ux;
-      // the FP32 sums are in y/z quanta: (u_x / u_r)^2 takes them to x quanta, like slong * u_x^2
-      const double us = sizeof(Real) == 4 ? (ph.ux / ph.ur) * (ph.ux / ph.ur) : u2;
-      st.cx[i] = Real(slong[i] * u2 + ax * us);
-      st.cy[i] = Real(slong[ph.N + i] * u2 + ay * us);
-      st.cz[i] = Real(slong[2 * (int64_t)ph.N + i] * u2 + az * us);
+      st.cx[i] = slong[i] * u2 + ax * u2;
+      st.cy[i] = slong[ph.N + i] * u2 + ay * u2;
+      st.cz[i] = slong[2 * (int64_t)ph.N + i] * u2 + az * u2;
     }
     __syncthreads();
+  }
+}
+
+// FP32 form, in y/z position quanta, with per-wave source lists.  One workgroup per cell, whose
+// targets (sorted by sub-cell key) are cut into clusters of kSrCluster consecutive targets; a wave
+// takes one cluster at a time, lane l pairing target l mod 8 of it with every 8th source of the
+// wave's list from l / 8 on.  The records of the 27 neighbouring cells are staged in LDS (in
+// chunks when they exceed it); for each staged chunk a wave lists the sources within r_max of its
+// cluster's bounding box (the distance from a point to a box is a lower bound of its distance to
+// every target in the box), so sources that cannot reach any target of the cluster are never
+// paired.  Every source left out would add an exact zero (it lies beyond r_max, where the profile
+// table ends in (0, 0)), so the set of contributing pairs is that of the 27-cell walk.  Each lane
+// sums its pairs of a chunk in FP32 in list order; the 8 lane sums of a target are added in FP64
+// by a butterfly and then to the target's long-range part (in FP64, chunk by chunk; the last
+// chunk writes the acceleration), a fixed order: the results are bitwise reproducible.  Pairs take
+// the tabulated profile from a copy of the table in LDS; overlapping pairs, which are rare, take
+// the exact clamp.  The list holds byte offsets of the staged records and is padded with a far,
+// uncharged dummy record (it adds an exact zero), so that every lane of the wave runs the same
+// iterations; the loop loads the next list entries and their records while it evaluates the
+// current ones.
+__global__ __launch_bounds__(kSrLanes) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_p3m_short_f32(State<float> st, Phys ph, P3mDev m,
+                                                            const int32_t *__restrict__ starts,
+                                                            const int32_t *__restrict__ sorted,
+                                                            const float4 *__restrict__ rec,
+                                                            const float *__restrict__ rad,
+                                                            double *__restrict__ slong,
+                                                            const float2 *__restrict__ tab) {
+  constexpr int CAP = kSrLdsF32 / (sizeof(float4) + sizeof(float)) - 1;
+  static_assert((CAP + 1) * sizeof(float4) <= 65536, "list entries are 16-bit byte offsets");
+  __shared__ float4 src[CAP + 1];   // entry CAP: the dummy record
+  __shared__ float srad[CAP + 1];
+  __shared__ float2 stab[kSrTable + 1];
+  __shared__ uint16_t list[kSrWaves][kSrList];
+  __shared__ int32_t rb[27], rn[27], roff[28];
+  const int c = blockIdx.x;
+  const int cz = c % m.ncy, cy = (c / m.ncy) % m.ncy, cx = c / (m.ncy * m.ncy);
+  const int t0 = starts[c], nt = starts[c + 1] - t0;
+  if (nt == 0) return;   // uniform: the whole workgroup leaves
+  for (int k = threadIdx.x; k <= kSrTable; k += kSrLanes) stab[k] = tab[k];   // read after the barriers below
+  if (threadIdx.x == 0) {
+    // far (r^2 ~ 1e36, finite) and uncharged: its pairs fall past the table's end and add 0
+    src[CAP] = make_float4(0.0f, 1.0e18f, 1.0e18f, 0.0f);
+    srad[CAP] = 0.0f;
+  }
+  neighbour_ranges(m, starts, cx, cy, cz, rb, rn, roff);
+  const int total = roff[27];
+  const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+  const int tl = lane & (kSrCluster - 1), sl = lane / kSrCluster;   // target in the cluster, slice
+  uint16_t *wl = list[wave];
+  // x differences scaled by u_x / u_r, alpha per quantum, table coordinate u = r * tq, the largest
+  // contact distance squared (uniform: held in scalar registers)
+  auto uniform = [](double v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int((float)v))); };
+  const float kx = uniform(ph.ux / ph.ur), aq = uniform(m.alpha * ph.ur), c2q = uniform(2.0 * m.alpha * ph.ur / sqrt(M_PI));
+  const float tq = uniform(kSrTable * ph.ur / m.rmax);
+  const float near2q = uniform(ph.near2 * (ph.ux / ph.ur) * (ph.ux / ph.ur));
+  // beyond this (r_max squared in quanta, plus 1e-4 for rounding) the table coordinate u is surely
+  // past the last interval, so the pair adds an exact zero
+  const float skip2q = uniform((m.rmax / ph.ur) * (m.rmax / ph.ur) * 1.0001);
+  // With at least 4 cells along x, three neighbouring cells cannot reach around the period, so an
+  // x offset taken relative to the cluster's first target is the pair's own minimum-image offset
+  // up to a whole period that puts the pair beyond r_max; with 3 cells the x extent is not used.
+  const bool use_x = m.ncx >= 4;
+  const int ncl = (nt + kSrCluster - 1) / kSrCluster;
+  const bool once = total <= CAP;   // all sources fit: staged once for the whole cell
+  const double u2 = ph.ux * ph.ux;
+  // the sums are in y/z quanta: 1 / u_r^2 takes them to the units of the long-range part
+  const double us = 1.0 / (ph.ur * ph.ur);
+  for (int pass = 0; pass < ncl; pass += kSrWaves * kSrRounds) {
+    for (int cb = 0; cb < total; cb += CAP) {
+      const int n = min(CAP, total - cb);
+      const bool last = cb + n >= total;
+      if (!once || pass == 0) stage_sources(rec, rad, rb, roff, cb, n, src, srad);
+#pragma unroll 1
+      for (int r = 0; r < kSrRounds; ++r) {
+        const int q = pass + r * kSrWaves + wave;   // this wave's cluster (wave-uniform)
+        if (q >= ncl) break;
+        const int ti = min(q * kSrCluster + tl, nt - 1);   // a short cluster repeats its last target
+        const float4 me = rec[t0 + ti];
+        const uint32_t mx = __float_as_uint(me.x);
+        const uint32_t xref = __float_as_uint(rec[t0 + q * kSrCluster].x);
+        // the cluster's bounding box (x relative to its first target), reduced over the 8 targets
+        float lo[3], hi[3];
+        lo[0] = hi[0] = (float)(int32_t)(mx - xref) * kx;
+        lo[1] = hi[1] = me.y;
+        lo[2] = hi[2] = me.z;
+#pragma unroll
+        for (int k = 1; k < kSrCluster; k <<= 1)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], k));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], k));
+          }
+        // the box is the same in every lane: kept in scalar registers
+        float bc[3], bh[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          bc[a] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(0.5f * (lo[a] + hi[a]))));
+          bh[a] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(0.5f * (hi[a] - lo[a]))));
+        }
+        if (!use_x) bh[0] = 3.0e38f;
+        float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+        int cnt = 0;   // entries in the wave's list (wave-uniform)
+        for (int e0 = 0; e0 < n; e0 += 64) {
+          const int e = e0 + lane;
+          bool ok = false;
+          if (e < n) {
+            const float4 s = src[e];
+            const float gx = fmaxf(fabsf((float)(int32_t)(__float_as_uint(s.x) - xref) * kx - bc[0]) - bh[0], 0.0f);
+            const float gy = fmaxf(fabsf(s.y - bc[1]) - bh[1], 0.0f);
+            const float gz = fmaxf(fabsf(s.z - bc[2]) - bh[2], 0.0f);
+            ok = fmaf(gx, gx, fmaf(gy, gy, gz * gz)) < skip2q;
+          }
+          const uint64_t mask = __builtin_amdgcn_ballot_w64(ok);
+          if (ok)
+            wl[cnt + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))] =
+                (uint16_t)(e * sizeof(float4));
+          cnt += __builtin_popcountll(mask);
+          if (cnt <= kSrList - 64 - 4 * kSrSlices && e0 + 64 < n) continue;
+          // pair the cluster with the listed sources, then empty the list: iterations of 8 entries,
+          // taken two at a time and loaded two iterations ahead, so the list is padded with 32
+          // dummy entries (every entry read lies below cnt + 32)
+          const int iters = (cnt + kSrSlices - 1) / kSrSlices;
+          if (lane < 4 * kSrSlices) wl[cnt + lane] = (uint16_t)(CAP * sizeof(float4));
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          auto pair = [&](const float4 cur, uint32_t off) {
+            // r2 carries 1e-20 (below the rounding of any r2 >= 1, i.e. of any two distinct
+            // positions) so that r = 0 (the target itself) gives a finite f times dx = 0
+            const float dx = (float)(int32_t)(mx - __float_as_uint(cur.x)) * kx;
+            const float dy = me.y - cur.y;
+            const float dz = me.z - cur.z;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, 1e-20f)));
+            if (!__builtin_amdgcn_ballot_w64(r2 < skip2q)) return;   // no lane within r_max
+            const float inv = __builtin_amdgcn_rsqf(r2);
+            const float rr = r2 * inv;
+            const float u = fminf(rr * tq, (float)kSrTable);   // u >= kSrTable: beyond r_max, entry (0, 0)
+            const float2 tv = stab[(int)u];
+            float f = cur.w * fmaf(__builtin_amdgcn_fractf(u), tv.y, tv.x) * ((inv * inv) * inv);
+            if (__builtin_amdgcn_ballot_w64(r2 < near2q)) {
+              // a pair of this source may overlap: clamped Coulomb minus the erf field, exactly
+              const float dij = rad[t0 + ti] + srad[off / sizeof(float4)];
+              if (r2 > 1e-20f && rr < dij) {
+                // 1/r = inv and 1/r^2 = inv^2 (from the rsq above, 1 ulp)
+                const float gg = c2q * expf(-aq * aq * r2) * inv;
+                f = cur.w * (1.0f / (dij * dij) - (erff(aq * rr) * (inv * inv) - gg)) * inv;
+              }
+            }
+            sx = fmaf(f, dx, sx);
+            sy = fmaf(f, dy, sy);
+            sz = fmaf(f, dz, sz);
+          };
+          auto rec_at = [&](uint32_t off) { return *(const float4 *)((const char *)src + off); };
+          uint32_t oa = wl[sl], ob = wl[kSrSlices + sl];
+          float4 sa = rec_at(oa), sb = rec_at(ob);
+          for (int k = 0; k < iters; k += 2) {
+            const uint32_t na = wl[(k + 2) * kSrSlices + sl], nb = wl[(k + 3) * kSrSlices + sl];
+            const float4 ca = sa, cb4 = sb;
+            const uint32_t pa = oa, pb = ob;
+            sa = rec_at(na);
+            sb = rec_at(nb);
+            oa = na;
+            ob = nb;
+            pair(ca, pa);
+            if (k + 1 < iters) pair(cb4, pb);
+          }
+          cnt = 0;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        // the 8 slices of each target, added in FP64 by a butterfly; slice 0 adds them to the
+        // long-range part, and after the last chunk writes the acceleration
+        double v[3] = {(double)sx, (double)sy, (double)sz};
+#pragma unroll
+        for (int k = kSrCluster; k < 64; k <<= 1)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) v[a] += __shfl_xor(v[a], k);
+        if (sl == 0 && q * kSrCluster + tl < nt) {
+          const int i = sorted[t0 + q * kSrCluster + tl];
+          const double lx = slong[i] + v[0] * us, ly = slong[ph.N + i] + v[1] * us,
+                       lz = slong[2 * (int64_t)ph.N + i] + v[2] * us;
+          if (last) {
+            st.cx[i] = (float)(lx * u2);
+            st.cy[i] = (float)(ly * u2);
+            st.cz[i] = (float)(lz * u2);
+          } else {
+            slong[i] = lx;
+            slong[ph.N + i] = ly;
+            slong[2 * (int64_t)ph.N + i] = lz;
+          }
+        }
+      }
+    }
   }
 }
 
@@ -807,10 +985,15 @@ template <class Real> void launch_p3m(const State<Real> &st, const Phys &ph, con
   fft3d<T>(m, work, +1, FftLines::kFieldInverse, kMul, FftSrc{rho, g2, nullptr, nullptr, nullptr, m.nc}, s);
   hipLaunchKernelGGL((k_p3m_interp<Real>), dim3(gp), dim3(256), 0, s, st, ph, m, m.sorted, work,
                      m.slong + 2 * (int64_t)ph.N, (double *)nullptr);
-  SrRec<Real> *rec = (SrRec<Real> *)m.rec;
-  hipLaunchKernelGGL((k_p3m_records<Real>), dim3(gp), dim3(256), 0, s, st, ph, m.sorted, rec);
-  hipLaunchKernelGGL((k_p3m_short<Real>), dim3(ncell), dim3(64 * kSrWaves), 0, s, st, ph, m, m.starts, m.sorted, rec,
-                     m.slong, m.table);
+  hipLaunchKernelGGL((k_p3m_records<Real>), dim3(gp), dim3(256), 0, s, st, ph, m.sorted, m.rec);
+  if constexpr (sizeof(Real) == 4) {
+    const float4 *rec = (const float4 *)m.rec;
+    hipLaunchKernelGGL(k_p3m_short_f32, dim3(ncell), dim3(kSrLanes), 0, s, st, ph, m, m.starts, m.sorted, rec,
+                       (const float *)(rec + ph.N), m.slong, m.table);
+  } else {
+    hipLaunchKernelGGL(k_p3m_short_f64, dim3(ncell), dim3(kSrLanes), 0, s, st, ph, m, m.starts, m.sorted,
+                       (const SrRec64 *)m.rec, m.slong);
+  }
 }
 
 template void launch_p3m<float>(const State<float> &, const Phys &, const P3mDev &, hipStream_t);
