@@ -410,6 +410,28 @@ __device__ __forceinline__ int3 sr_cell(const State<Real> &st, const Phys &ph, c
   return make_int3(cx, cy, cz);
 }
 
+// Adds 1 to ctr[key] for every active lane with one atomic per distinct key in the wave (the
+// particles of a wave often share a cell: the storage follows the cells).  Returns the counter's
+// value before the lane's own increment; the lanes of one key take consecutive values in lane
+// order.  Lanes outside the execution mask take no part.
+__device__ __forceinline__ int32_t wave_count_add(int32_t *__restrict__ ctr, int key, bool active) {
+  const int lane = (int)(threadIdx.x & 63);
+  uint64_t todo = __builtin_amdgcn_ballot_w64(active);
+  int32_t mine = 0;
+  while (todo) {
+    const int leader = __builtin_ctzll(todo);
+    const int lkey = __builtin_amdgcn_readlane(key, leader);
+    const uint64_t grp = __builtin_amdgcn_ballot_w64(active && key == lkey) & todo;
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(ctr + lkey, (int32_t)__builtin_popcountll(grp));
+    base = __builtin_amdgcn_readlane(base, leader);
+    if ((grp >> lane) & 1)
+      mine = base + (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(grp >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)grp, 0u));
+    todo &= ~grp;
+  }
+  return mine;
+}
+
 // Cell id and sub-cell key of the particle, packed as 64 id + key.  The key orders the 4 x 4 x 4
 // sub-cells of a cell along a Morton curve (bits: the halves along x, y, z, then the quarters
 // within them), so that consecutive particles of the cell-sorted order lie close together.
@@ -429,7 +451,7 @@ __global__ void k_p3m_bin(State<Real> st, Phys ph, P3mDev m, int32_t *__restrict
             qz = quarter((z + ph.R) / (2.0 * ph.R) * m.ncy - c.z);
   const int key = ((qx >> 1) << 5) | ((qy >> 1) << 4) | ((qz >> 1) << 3) | ((qx & 1) << 2) | ((qy & 1) << 1) | (qz & 1);
   cell_of[i] = 64 * id + key;
-  atomicAdd(counts + id, 1);
+  wave_count_add(counts, id, true);
 }
 
 // Exclusive scan of the cell counts by one workgroup; starts[ncell] = N; fill pointers copied.
@@ -461,8 +483,9 @@ __global__ __launch_bounds__(1024) void k_p3m_scan(int32_t ncell, const int32_t 
 __global__ void k_p3m_scatter(int32_t N, const int32_t *__restrict__ cell_of, int32_t *__restrict__ fill,
                               int32_t *__restrict__ sorted) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  sorted[atomicAdd(fill + (cell_of[i] >> 6), 1)] = i;
+  const bool active = i < N;
+  const int slot = wave_count_add(fill, active ? cell_of[i] >> 6 : 0, active);
+  if (active) sorted[slot] = i;
 }
 
 // Particles of each cell ordered by (sub-cell key, index): a fixed summation order in which
