@@ -210,3 +210,48 @@ def test_p3m_single_65k_sampled_against_lattice_sum_and_steps():
     sim2.step(10)
     t = sim2.tally()[0]
     assert t["n_alive"] + t["n_dep"] == w.n_particles and np.all(np.isfinite(sim2.read()["a"]))
+
+
+@pytest.mark.parametrize("real_bytes", [8, 4])
+def test_p3m_storage_reorder_keeps_the_trajectory(real_bytes):
+    """P3M with every other force on, the particle storage permuted into cell order every 3 steps against
+    none (the P3M cell lists, their per-wave counters and the short-range lists are rebuilt from the
+    storage at every evaluation): the depositing 1,024-particle variant (3 short-range cells along x) and
+    6,000 particles of the 65k recipe (17 cells along x), 30 steps.  Every particle, in the caller's
+    order, at the same place (FP64: 1e-13 R; FP32: 1e-6 R, sums that follow the storage order round
+    differently) and the same deposition steps (FP32: at most one particle whose event moved by a step,
+    counted and left out of the position check).  Where each 4 x 4 x 4 sub-cell of the P3M cells holds at
+    most one particle, as here, the P3M summation order does not depend on the storage and the two runs
+    agree bitwise."""
+    from paper_2205_04979_amd.depo import Simulation
+    from tests.gpu_common import position_error
+    cases = [(make_workload("plain-1k-dep"), dict(mesh_x=32, mesh_yz=16, alpha_h=0.5, rmax_alpha=3.5)),
+             (make_workload("single-65k", n=6000, field_n=32), dict(mesh_x=128, mesh_yz=64, alpha_h=0.5,
+                                                                     rmax_alpha=3.5))]
+    for w, cfg in cases:
+        f = w.field()
+        say("case: p3m storage reorder,", w.name, w.n_particles, "fp", 8 * real_bytes)
+        runs = {}
+        for every in (0, 3):
+            sim = Simulation(w.params, w.offsets, f.shape[:3], real_bytes=real_bytes, p3m=cfg)
+            sim.init_field(f)
+            sim.seed(w.sample_params, w.x, w.d, w.qbase)
+            sim.set_reorder(every)
+            sim.step(30)
+            runs[every] = sim.read()
+            # the storage permutation, as the checkpoint blob carries it (after a 48-byte header: positions,
+            # 12 per-particle reals, 3 doubles and the deposition step, then the permutation)
+            n = w.n_particles
+            off = 48 + n * (3 * real_bytes + 12 * real_bytes + 3 * 8 + 4)
+            perm = np.frombuffer(sim.state_download(), dtype=np.int32, count=n, offset=off)
+            assert np.array_equal(np.sort(perm), np.arange(n))
+            assert np.array_equal(perm, np.arange(n)) == (every == 0), "reordered storage expected"
+            sim.close()
+        a, b = runs[0], runs[3]
+        moved = a["dep_step"] != b["dep_step"]
+        say("deposited", int((a["dep_step"] > 0).sum()), "events moved", int(moved.sum()))
+        assert moved.sum() == 0 if real_bytes == 8 else moved.sum() <= 1
+        both = (a["dep_step"] == 0) & (b["dep_step"] == 0)
+        err = position_error(b["x"][both], a["x"][both], w.params["L"], w.params["R"])
+        say("reordered vs fixed order: max |dx|/R", err.max())
+        assert err.max() < (1e-13 if real_bytes == 8 else 1e-6)
