@@ -255,3 +255,32 @@ def test_p3m_storage_reorder_keeps_the_trajectory(real_bytes):
         err = position_error(b["x"][both], a["x"][both], w.params["L"], w.params["R"])
         say("reordered vs fixed order: max |dx|/R", err.max())
         assert err.max() < (1e-13 if real_bytes == 8 else 1e-6)
+
+
+@pytest.mark.parametrize("real_bytes", [8, 4])
+def test_p3m_crowded_cells_against_oracle_p3m(real_bytes):
+    """Large P3M cells: 12,300 particles on a 32 x 16 mesh, whose r_max leaves 3 short-range cells of
+    about 4,100 particles each.  This takes the kernels' large-cell paths: the one-thread sort of cells
+    above 2,048 particles, several staged chunks of the 27-cell neighbourhood and several target passes
+    (FP32: 4,096 targets per pass, one cell holds 4,122; FP64: 512 per block).  Every particle against
+    the FP64 P3M oracle, relative to sum_j |a_ij|: FP64 1e-9, FP32 the stated per-particle bound."""
+    from tests.oracle_pool import pooled_coulomb_scale, pooled_nearest
+    from oracle.sim import OracleSim
+    w = make_workload("single-65k", n=12300, field_n=16, **COULOMB_ONLY)
+    f = w.field()
+    cfg = dict(mesh_x=32, mesh_yz=16, alpha_h=0.5, rmax_alpha=3.5)
+    say("case: p3m crowded cells, n=12300, fp", 8 * real_bytes)
+    sim, g = gpu_accel(w, f, real_bytes, cfg)
+    mesh = op3m.Mesh(w.params["R"], w.params["L"], 32, 16, 0.5, 3.5)
+    q = w.sample_params[0, 0] * w.qbase
+    S = op3m.p3m_sums(mesh, g["x"], q, w.d)
+    a_ora = accel_from_sums(w.params, w.sample_params, w.qbase, w.d, S)
+    ora = OracleSim(w.params, f, g["x"], w.d, w.qbase, w.offsets, w.sample_params, evaluate=False)
+    tg = np.arange(w.n_particles)
+    e = np.linalg.norm(g["a"] - a_ora, axis=1) / pooled_coulomb_scale(ora, tg)
+    say("per particle: max", e.max(), "median", np.median(e))
+    if real_bytes == 8:
+        assert e.max() < 1e-9
+    else:
+        assert np.all(e <= p3m_fp32_bound(w, pooled_nearest(ora, tg)))
+    sim.close()
