@@ -434,6 +434,67 @@ def lf_run() -> dict:
     return res
 
 
+def mfmc_run(budget: float = 36.0, n_pilot: int = 16, hf_steps: int = 200) -> dict:
+    """The multi-fidelity estimator of Section 3 end to end on the GPU models: V_dep+ of the particle
+    step (16,384 particles of the temperature-study recipe, rebound law, 200 steps of 1e-5 s; every
+    input point one sample of one batched launch) as the high-fidelity model and the one-dimensional
+    Eulerian model (d = 10 um) as the low-fidelity one, inputs (xi, zeta, T) with xi ~ U[0, 0.1],
+    zeta ~ U[0, 1], T ~ U[1000, 1889] K.  A pilot of 16 points on both models gives sigma, rho_12 and
+    the cost ratio (measured wall time per point); the budget of 36 high-fidelity runs (the budget
+    of Table 3) is split as p / (d + 2) for the Sobol' indices; the whole estimator is timed."""
+    import torch
+    from paper_2205_04979_amd import mfmc as pmf
+    from synthetic import make_workload
+    w = make_workload("rebound-theta-64", n_samples=1, steps=hf_steps)
+    field = w.field()
+    hf = pmf.HighFidelityGPU(w.params, field, w.x, w.d, steps=hf_steps, real_bytes=4)
+    lf = pmf.LowFidelityGPU(w.params, 10e-6)
+
+    def sample(rng, m):
+        return np.stack([rng.uniform(0.0, 0.1, m), rng.uniform(0.0, 1.0, m),
+                         1000.0 + 200.0 * rng.uniform(0.0, 1.0, m) / 0.225], axis=1)
+
+    log(f"[bench] mfmc: HF {w.n_particles} particles x {hf_steps} steps per input point, pilot {n_pilot}")
+    hf(sample(np.random.default_rng(20), 2))          # warm the kernels up
+    lf(sample(np.random.default_rng(20), 2))
+    pilot = sample(np.random.default_rng(21), n_pilot)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    yh = hf(pilot)
+    t1 = time.perf_counter()
+    yl = lf(pilot)
+    t2 = time.perf_counter()
+    w_hf, w_lf = (t1 - t0) / n_pilot, (t2 - t1) / n_pilot
+    sigma = (float(yh.std(ddof=1)), float(yl.std(ddof=1)))
+    rho12 = float(np.corrcoef(yh, yl)[0, 1])
+    res = {"hf_particles": w.n_particles, "hf_steps": hf_steps, "dt": w.params["dt"], "pilot": n_pilot,
+           "sigma": sigma, "rho12": rho12, "hf_s_per_point_in_pilot": round(w_hf, 5),
+           "lf_s_per_point_in_pilot": round(w_lf, 6), "budget_hf_runs": budget, "inputs": 3}
+    try:
+        t3 = time.perf_counter()
+        r = pmf.mfmc_sobol([hf, lf], sigma, (1.0, rho12), (1.0, w_lf / w_hf), budget, sample, 3,
+                           np.random.default_rng(22))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t3
+        m1, m2 = int(r.counts[0]), int(r.counts[1])
+        res.update({"counts": [m1, m2], "alpha": [float(a) for a in r.alpha], "wall_s": round(wall, 4),
+                    "hf_points": 5 * m1, "lf_points": 5 * m2,
+                    "hf_particle_steps_per_s": round(5 * m1 * w.n_particles * hf_steps / wall, 1),
+                    "mean_vdep_plus": r.mean, "variance": r.variance,
+                    "main_effects": [float(v) for v in r.main], "total_effects": [float(v) for v in r.total],
+                    "gamma_predicted": pmf.gamma(abs(rho12), 1.0, w_lf / w_hf) if abs(rho12) < 1 else None,
+                    "precondition_holds": bool(pmf.precondition_holds((1.0, rho12), (1.0, w_lf / w_hf))),
+                    "note": "one batched HF launch and one LF launch per estimator call; wall_s includes "
+                            "seeding, field upload and tally readback of the HF batch; the indices come from "
+                            "m1 = counts[0] HF samples, so the estimators (Owen's main effect can be negative) "
+                            "are noisy at this budget"})
+    except ValueError as e:   # degenerate pilot statistics
+        res["error"] = str(e)
+    log(f"[bench] mfmc: {res}")
+    torch.cuda.empty_cache()
+    return res
+
+
 P3M_CONFIGS = {"single-65k": dict(mesh_x=128, mesh_yz=64, alpha_h=0.5, rmax_alpha=3.5),
                "large-1m": dict(mesh_x=256, mesh_yz=128, alpha_h=0.5, rmax_alpha=3.5)}
 
@@ -496,7 +557,7 @@ def main():
                     help="particles of the workload the CPU oracle steps once (capped at the workload size)")
     ap.add_argument("--kernel", default=None, help="pair-kernel shape ipl,waves,block (skips autotuning)")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--legs", default="single,batched,adjoint,rebound,plain,lf,p3m,large",
+    ap.add_argument("--legs", default="single,batched,adjoint,rebound,plain,lf,mfmc,p3m,large",
                     help="which measurements to run: single (the headline), batched, adjoint, rebound, plain, lf, "
                          "p3m, large")
     ap.add_argument("--secondary-steps", type=int, default=1000,
@@ -546,6 +607,8 @@ def main():
             out["plain"] = plain_run()
         if "lf" in legs:
             out["lf"] = lf_run()
+        if "mfmc" in legs:
+            out["mfmc"] = mfmc_run()
         if "p3m" in legs:
             out["p3m"] = p3m_run(args.p3m_steps, p3m_names)
         if "large" in legs:
@@ -667,6 +730,8 @@ def main():
             out["plain"] = plain_run()
         if "lf" in legs:
             out["lf"] = lf_run()
+        if "mfmc" in legs:
+            out["mfmc"] = mfmc_run()
         if "p3m" in legs:
             out["p3m"] = p3m_run(args.p3m_steps, p3m_names)
         if "large" in legs:
