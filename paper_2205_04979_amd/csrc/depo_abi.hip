@@ -382,19 +382,22 @@ int64_t count_items(const std::vector<int64_t> &off, int64_t T) {
   return total;
 }
 
-template <class Real> void enqueue_coulomb(depo_ctx *ctx, hipStream_t s) {
-  if (!(ctx->p.flags & DEPO_COULOMB)) return;
+// Returns the k_finish mode bit that the pair sums need: with defer_finish, the symmetric pair
+// kernel leaves its fixed-point accumulators to k_finish (F_PAIR_SUMS), one pass fewer per step.
+template <class Real> int enqueue_coulomb(depo_ctx *ctx, hipStream_t s, bool defer_finish = false) {
+  if (!(ctx->p.flags & DEPO_COULOMB)) return 0;
   if (ctx->p3m_use) {
     launch_p3m<Real>(state<Real>(ctx), ctx->ph, ctx->pm, s);
-    return;
+    return 0;
   }
   if constexpr (std::is_same<Real, float>::value) {
     if (ctx->ccfg.symmetric) {
-      launch_coulomb_sym(ctx->sf, ctx->ph, ctx->n_diag, ctx->n_off, ctx->ccfg, s);
-      return;
+      launch_coulomb_sym(ctx->sf, ctx->ph, ctx->n_diag, ctx->n_off, ctx->ccfg, s, defer_finish);
+      return defer_finish ? F_PAIR_SUMS : 0;
     }
   }
   launch_coulomb<Real>(state<Real>(ctx), ctx->ph, ctx->n_tiles, ctx->ccfg, s);
+  return 0;
 }
 
 // Enqueue the force evaluation at the current positions (prepare has run).
@@ -423,8 +426,10 @@ template <class Real> void enqueue_step(depo_ctx *ctx, hipStream_t s) {
   const State<Real> &st = state<Real>(ctx);
   enqueue_order<Real>(ctx, s);
   launch_prepare<Real>(st, ctx->ph, prepare_mode(ctx) | P_KICK_DRIFT, s);
-  enqueue_forces<Real>(ctx, s);
-  launch_finish<Real>(st, ctx->ph, F_KICK, s);
+  if (short_range_on(ctx)) launch_cells<Real>(st, ctx->ph, ctx->n_cells, (ctx->n_cells + 1023) / 1024, s);
+  const int pair_mode = enqueue_coulomb<Real>(ctx, s, true);
+  if (short_range_on(ctx)) launch_short_range<Real>(st, ctx->ph, ctx->n_cells, s);
+  launch_finish<Real>(st, ctx->ph, F_KICK | pair_mode, s);
 }
 
 // One step as a graph with two branches after prepare: the direct Coulomb sums, and the cell
@@ -441,9 +446,9 @@ template <class Real> hipError_t capture_forked_step(depo_ctx *ctx) {
   launch_cells<Real>(st, ctx->ph, ctx->n_cells, (ctx->n_cells + 1023) / 1024, b);
   launch_short_range<Real>(st, ctx->ph, ctx->n_cells, b);
   if ((e = hipEventRecord(ctx->ev_join, b)) != hipSuccess) return e;
-  enqueue_coulomb<Real>(ctx, a);
+  const int pair_mode = enqueue_coulomb<Real>(ctx, a, true);
   if ((e = hipStreamWaitEvent(a, ctx->ev_join, 0)) != hipSuccess) return e;
-  launch_finish<Real>(st, ctx->ph, F_KICK, a);
+  launch_finish<Real>(st, ctx->ph, F_KICK | pair_mode, a);
   return hipGetLastError();
 }
 

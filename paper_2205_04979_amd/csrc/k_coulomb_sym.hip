@@ -256,7 +256,7 @@ bool coulomb_sym_supported(const CoulombConfig &cfg) {
 }
 
 void launch_coulomb_sym(const State<float> &st, const Phys &ph, int n_diag, int n_off, const CoulombConfig &cfg,
-                        hipStream_t s) {
+                        hipStream_t s, bool defer_finish) {
   const float near2 = (float)ph.near2;
   const int n_items = n_diag + n_off;
 #define X(I, W)                                                                                              \
@@ -270,7 +270,7 @@ void launch_coulomb_sym(const State<float> &st, const Phys &ph, int n_diag, int 
   }
   DEPO_COULOMB_SYM_CASES(X)
 #undef X
-  if (ph.N > 0)
+  if (ph.N > 0 && !defer_finish)
     hipLaunchKernelGGL(k_pair_finish, dim3((ph.N + 255) / 256), dim3(256), 0, s, ph.N, st.sid, st.fx_scale, st.accx,
                        st.accy, st.accz, st.cx, st.cy, st.cz);
 }

@@ -184,6 +184,21 @@ __global__ __launch_bounds__(256) void k_finish(State<Real> st, Phys ph, int mod
   // the step counter advances once per step; no thread of this kernel reads it
   if ((mode & F_KICK) && i == 0) *st.nstep += 1;
   if (i >= ph.N) return;
+  Real cs[3];   // Coulomb pair sums of this particle
+  if constexpr (sizeof(Real) == 4) {
+    if (mode & F_PAIR_SUMS) {
+      // fixed point -> FP32 and the accumulators cleared, for removed particles too (the pair kernel
+      // adds to every target of its items)
+      const double inv = 1.0 / st.fx_scale[st.sid[i]];
+      cs[0] = (Real)((double)(long long)st.accx[i] * inv);
+      cs[1] = (Real)((double)(long long)st.accy[i] * inv);
+      cs[2] = (Real)((double)(long long)st.accz[i] * inv);
+      st.accx[i] = 0ull;
+      st.accy[i] = 0ull;
+      st.accz[i] = 0ull;
+      st.cx[i] = cs[0]; st.cy[i] = cs[1]; st.cz[i] = cs[2];
+    }
+  }
   if (st.dep[i] != 0) return;
   if (mode & F_FLUID_ONLY) {
     Real u[3];
@@ -199,8 +214,11 @@ __global__ __launch_bounds__(256) void k_finish(State<Real> st, Phys ph, int mod
   const double q = sp.charge_scale * st.qb[i];
   Real a[3] = {0, 0, 0};
   if (ph.flags & F_COULOMB) {
+    if (!(sizeof(Real) == 4 && (mode & F_PAIR_SUMS))) {
+      cs[0] = st.cx[i]; cs[1] = st.cy[i]; cs[2] = st.cz[i];
+    }
     const Real c = Real(ph.k_e * q * ph.q_ref / (m * ph.ux * ph.ux));
-    a[0] += c * st.cx[i]; a[1] += c * st.cy[i]; a[2] += c * st.cz[i];
+    a[0] += c * cs[0]; a[1] += c * cs[1]; a[2] += c * cs[2];
   }
   if (ph.flags & (F_COLLIDE | F_VDW)) {
     a[0] += st.sx[i]; a[1] += st.sy[i]; a[2] += st.sz[i];

@@ -8,7 +8,9 @@ namespace depo {
 // k_prepare modes
 enum : int { P_KICK_DRIFT = 1, P_COULOMB = 2, P_CELLS = 4, P_SEED = 8 };
 // k_finish modes
-enum : int { F_KICK = 1, F_V_FROM_FLUID = 2, F_FLUID_ONLY = 4 };
+// F_PAIR_SUMS (FP32): the symmetric pair kernel ran without its own finishing pass; k_finish turns
+// the fixed-point accumulators into the FP32 Coulomb sums and clears them, every particle's
+enum : int { F_KICK = 1, F_V_FROM_FLUID = 2, F_FLUID_ONLY = 4, F_PAIR_SUMS = 8 };
 
 template <class Real> void launch_prepare(const State<Real> &st, const Phys &ph, int mode, hipStream_t s);
 template <class Real> void launch_finish(const State<Real> &st, const Phys &ph, int mode, hipStream_t s);
@@ -43,8 +45,10 @@ bool coulomb_config_supported(int real_bytes, const CoulombConfig &cfg);
 // reduction of each particle's partial slots into cx/cy/cz.
 int coulomb_sym_tile(const CoulombConfig &cfg);   // targets (= sources) per item
 bool coulomb_sym_supported(const CoulombConfig &cfg);
+// defer_finish: leave the fixed-point accumulators for k_finish (mode F_PAIR_SUMS) instead of
+// converting them with k_pair_finish
 void launch_coulomb_sym(const State<float> &st, const Phys &ph, int n_diag, int n_off, const CoulombConfig &cfg,
-                        hipStream_t s);
+                        hipStream_t s, bool defer_finish = false);
 
 // P3M electrostatics (single-sample layouts): mesh geometry, splitting and workspace.
 struct P3mDev {
