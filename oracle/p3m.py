@@ -190,12 +190,14 @@ def mesh_field(mesh, x, q, ghat=None):
     return interpolate(mesh, E, x)
 
 
-def short_range(mesh, x, q, d):
-    """Short-range part over nearest-image pairs closer than r_max: Coulomb (overlap clamp) minus E_l."""
+def short_range(mesh, x, q, d, targets=None):
+    """Short-range part over nearest-image pairs closer than r_max: Coulomb (overlap clamp) minus E_l.
+    Rows for every particle, or for the particles listed in ``targets`` (every particle is a source)."""
     n = x.shape[0]
-    S = np.zeros((n, 3))
+    targets = np.arange(n) if targets is None else np.asarray(targets, dtype=np.int64)
+    S = np.zeros((targets.shape[0], 3))
     a = mesh.alpha
-    for i in range(n):
+    for k, i in enumerate(targets):
         r = x[i] - x
         r[:, 0] -= mesh.L * np.round(r[:, 0] / mesh.L)
         rr = np.sqrt(np.sum(r * r, axis=1))
@@ -206,7 +208,7 @@ def short_range(mesh, x, q, d):
         dij = 0.5 * (d[i] + d[sel])
         full = 1.0 / np.maximum(rs, dij) ** 2
         lng = erf(a * rs) / rs ** 2 - 2.0 * a / math.sqrt(math.pi) * np.exp(-(a * rs) ** 2) / rs
-        S[i] += ((qs * (full - lng) / rs)[:, None] * r[sel]).sum(axis=0)
+        S[k] += ((qs * (full - lng) / rs)[:, None] * r[sel]).sum(axis=0)
     return S
 
 

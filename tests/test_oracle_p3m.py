@@ -82,3 +82,16 @@ def test_p3m_converges_to_the_lattice_sum(system):
         errs.append(_rel_rms(p3m.p3m_sums(mesh, x, q, d), S))
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 2e-3
+
+
+def test_short_range_rows_for_listed_targets(system):
+    """The short range evaluated for listed targets gives exactly those rows of the full evaluation
+    (same pairs, same order), and a particle with no source within r_max gets zero."""
+    x, q, d, _ = system
+    mesh = p3m.Mesh(R, L, 16, 16, 0.5, 3.5)
+    full = p3m.short_range(mesh, x, q, d)
+    tg = np.array([5, 0, 17, 5, x.shape[0] - 1])
+    assert np.array_equal(p3m.short_range(mesh, x, q, d, tg), full[tg])
+    assert 0.5 * L > mesh.rmax
+    lone = p3m.short_range(mesh, np.array([[0.0, 0.0, 0.0], [0.5 * L, 0.0, 0.0]]), np.ones(2), np.full(2, 1e-5))
+    assert np.all(lone == 0.0)
