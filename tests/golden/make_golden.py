@@ -10,6 +10,7 @@ Usage (from the repository root)::
     python tests/golden/make_golden.py single65k   # 20 steps of the 65,536-particle workload
     python tests/golden/make_golden.py large4096   # 500 steps of 4,096 particles of the 2^20 recipe
     python tests/golden/make_golden.py p3m65k      # P3M sums of the 65,536-particle workload at seed
+    python tests/golden/make_golden.py p3m1m       # P3M sums of 4,096 targets of the 2^20 workload at seed
 
 Each file also stores a digest of the inputs it was made from, so a test can
 tell when the generator of a workload has changed since.
@@ -103,7 +104,50 @@ def p3m65k():
     print("wrote p3m_single65k_seed.npz", flush=True)
 
 
-JOBS = {"single65k": single65k, "large4096": large4096, "p3m65k": p3m65k}
+P3M_1M = dict(mesh_x=256, mesh_yz=128, alpha_h=0.5, rmax_alpha=3.5)
+P3M_1M_TARGETS = np.arange(0, 1 << 20, 256)
+
+
+def p3m1m():
+    """P3M sums S_i of the 4,096 targets i = 0 mod 256 of the 2^20-particle workload at its seeded
+    positions (every particle a source), with the benchmark's mesh (256 x 256 x 256 padded, alpha h =
+    0.5, r_max = 3.5 / alpha), the normaliser sum_j |a_ij| of the direct sum and each target's distance
+    to its nearest neighbour."""
+    from oracle import p3m as op3m
+    from oracle.sim import OracleSim
+    from synthetic import make_workload
+    from tests.oracle_pool import pooled_coulomb_scale, pooled_nearest
+    w = make_workload("large-1m")
+    f = w.field()
+    t0 = time.perf_counter()
+    c = P3M_1M
+    tg = P3M_1M_TARGETS
+    mesh = op3m.Mesh(w.params["R"], w.params["L"], c["mesh_x"], c["mesh_yz"], c["alpha_h"], c["rmax_alpha"])
+    q = w.sample_params[0, 0] * w.qbase
+    x = np.array(w.x)
+    x[:, 0] = np.mod(x[:, 0], w.params["L"])
+    ghat = op3m.green_hat(mesh)
+    print(f"green's function: {time.perf_counter() - t0:.1f} s", flush=True)
+    rho_hat = np.fft.fftn(op3m.assign(mesh, x, q))
+    E = [np.real(np.fft.ifftn(rho_hat * ghat[k])) for k in range(3)]
+    del ghat, rho_hat
+    long = op3m.interpolate(mesh, E, x[tg])
+    del E
+    print(f"mesh field: {time.perf_counter() - t0:.1f} s", flush=True)
+    short = op3m.short_range(mesh, x, q, w.d, tg)
+    print(f"short range: {time.perf_counter() - t0:.1f} s", flush=True)
+    sim = OracleSim(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, evaluate=False)
+    scale = pooled_coulomb_scale(sim, tg)
+    r_min = pooled_nearest(sim, tg)
+    print(f"normaliser and nearest sources: {time.perf_counter() - t0:.1f} s", flush=True)
+    np.savez_compressed(os.path.join(HERE, "p3m_large1m_seed_targets.npz"), S=long + short, scale=scale,
+                        r_min=r_min, targets=tg,
+                        config=np.array([c["mesh_x"], c["mesh_yz"], c["alpha_h"], c["rmax_alpha"]]),
+                        digest=np.array(input_digest(w, f)))
+    print("wrote p3m_large1m_seed_targets.npz", flush=True)
+
+
+JOBS = {"single65k": single65k, "large4096": large4096, "p3m65k": p3m65k, "p3m1m": p3m1m}
 
 if __name__ == "__main__":
     for job in sys.argv[1:] or list(JOBS):

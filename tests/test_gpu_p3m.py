@@ -109,6 +109,41 @@ def test_p3m_single_65k_every_particle_against_stored_p3m_oracle(real_bytes):
         assert np.median(e) < 1e-6
 
 
+@pytest.mark.parametrize("real_bytes", [8, 4])
+def test_p3m_large_1m_targets_against_stored_p3m_oracle(real_bytes):
+    """The 2^20-particle workload in the P3M configuration the benchmark times (mesh 256 x 256 x 256
+    with the zero padding, alpha h = 0.5, r_max = 3.5 / alpha), at seed: the accelerations of the 4,096
+    targets i = 0 mod 256 against the P3M oracle (stored by tests/golden/make_golden.py from the same
+    seeded inputs, every particle a source), relative to sum_j |a_ij|.  FP64: 1e-9 per target.  FP32:
+    the stated per-target bound."""
+    import os
+    from tests.golden.make_golden import P3M_1M, P3M_1M_TARGETS, input_digest
+    w = make_workload("large-1m")
+    f = w.field()
+    gold = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "p3m_large1m_seed_targets.npz"))
+    assert str(gold["digest"]) == input_digest(w, f)
+    cfg = dict(P3M_1M)
+    assert np.array_equal(gold["config"], [cfg["mesh_x"], cfg["mesh_yz"], cfg["alpha_h"], cfg["rmax_alpha"]])
+    tg = P3M_1M_TARGETS
+    assert np.array_equal(gold["targets"], tg)
+    say("case: p3m large-1m targets vs stored p3m oracle, fp", 8 * real_bytes)
+    wc = make_workload("large-1m", **COULOMB_ONLY)
+    sim, g = gpu_accel(wc, f, real_bytes, cfg)
+    a_ora = accel_from_sums(w.params, w.sample_params, w.qbase[tg], w.d[tg], gold["S"])
+    e = np.linalg.norm(g["a"][tg] - a_ora, axis=1) / gold["scale"]
+    k = int(np.argmax(e))
+    say(f"per target: max {e.max():.3e} (target {int(tg[k])}, nearest {gold['r_min'][k]:.3e} m), "
+        f"median {np.median(e):.3e}")
+    if real_bytes == 8:
+        assert e.max() < 1e-9
+    else:
+        bound = p3m_fp32_bound(w, gold["r_min"])
+        say("largest error / bound", float(np.max(e / bound)))
+        assert np.all(e <= bound)
+        assert np.median(e) < 1e-6
+    sim.close()
+
+
 def test_p3m_close_to_the_lattice_sum_and_deterministic():
     """Against the exact lattice sum (brute force over 100 x images; the tail beyond is ~1e-8 of the
     field): relative RMS error at the level of the oracle's pinned P3M accuracy; repeated runs are
