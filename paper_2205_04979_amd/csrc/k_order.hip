@@ -23,7 +23,7 @@ namespace depo {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kPer = 4;                       // slots per thread
+constexpr int kPer = 4;                       // slots per thread, kThreads apart (consecutive lanes, consecutive slots)
 constexpr int kBlock = kThreads * kPer;       // slots per block of the count and scatter passes
 
 __device__ __forceinline__ bool due(const int32_t *nstep, int every) {
@@ -62,10 +62,13 @@ template <class Real>
 __global__ __launch_bounds__(kThreads) void k_order_count(State<Real> st, int n, int every) {
   if (!due(st.nstep, every)) return;
   __shared__ int sh[kThreads];
-  const int base = blockIdx.x * kBlock + threadIdx.x * kPer;
+  const int base = blockIdx.x * kBlock + threadIdx.x;
   int c = 0;
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) c += (base + q < n && st.dep[base + q] != 0) ? 1 : 0;
+  for (int q = 0; q < kPer; ++q) {
+    const int i = base + q * kThreads;
+    c += (i < n && st.dep[i] != 0) ? 1 : 0;
+  }
   int total;
   block_scan(c, sh, total);
   if (threadIdx.x == 0) st.scan_part[blockIdx.x] = total;
@@ -92,29 +95,24 @@ template <class Real>
 __global__ __launch_bounds__(kThreads) void k_order_scatter(State<Real> st, OrderScratch<Real> sc, int n, int every) {
   if (!due(st.nstep, every)) return;
   __shared__ int sh[kThreads];
-  const int base = blockIdx.x * kBlock + threadIdx.x * kPer;
-  bool dead[kPer];
-  int c = 0;
+  const int base = blockIdx.x * kBlock + threadIdx.x;
+  int run = st.scan_part[blockIdx.x];   // removed particles in the slots before this row of the block
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
-    dead[q] = base + q < n && st.dep[base + q] != 0;
-    c += dead[q] ? 1 : 0;
-  }
-  int total;
-  int rank = st.scan_part[blockIdx.x] + block_scan(c, sh, total);   // removed particles in slots < base
-#pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int i = base + q;
-    if (i >= n) break;
+    const int i = base + q * kThreads;
+    const bool dead = i < n && st.dep[i] != 0;
+    int total;
+    const int rank = run + block_scan(dead ? 1 : 0, sh, total);   // removed particles in slots < i
+    run += total;
+    if (i >= n) continue;
     const SampleDev sp = st.samples[st.sid[i]];
     const int a0 = st.cell_start[sp.cell_base];                              // alive before the sample
     const int a1 = st.cell_start[sp.cell_base + sp.ncx * sp.ncy * sp.ncz];   // ... and up to its end
     int k;
-    if (dead[q]) {
+    if (dead) {
       // alive slots of the sample first, then its removed particles in slot order; sp.start - a0
       // removed particles precede the sample
       k = sp.start + (a1 - a0) + (rank - (sp.start - a0));
-      ++rank;
     } else {
       k = sp.start + (st.cell_of[i] - a0);
     }
