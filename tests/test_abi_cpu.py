@@ -253,3 +253,17 @@ def test_p3m_configuration_validation(depo):
     assert L.depo_set_p3m(coarse._h, 16, 16, 0.3, 6.0) == depo.OK                        # r_max > L / 3
     with pytest.raises(depo.DepoError):
         coarse.set_layout([0, 1000], 16, 16, 16)
+
+
+def test_reorder_interval_validation(depo):
+    """depo_set_reorder takes 0 (never) to 2^20 steps; anything else, and a null context, is rejected
+    (with a message where there is a context)."""
+    ctx = depo.Context(physical_params(), 4)
+    L = depo.lib()
+    assert L.depo_set_reorder(ctx._h, 16) == depo.OK
+    assert L.depo_set_reorder(ctx._h, 0) == depo.OK
+    assert L.depo_set_reorder(ctx._h, 1 << 20) == depo.OK
+    for bad in (-1, (1 << 20) + 1):
+        assert L.depo_set_reorder(ctx._h, bad) == depo.E_INVALID
+        assert b"reorder" in L.depo_last_error(ctx._h)
+    assert L.depo_set_reorder(None, 4) == depo.E_INVALID
