@@ -791,3 +791,22 @@ def test_layout_without_particles(real_bytes):
     t = sim.tally()
     assert len(t) == 2 and all(x["n_alive"] == 0 and x["n_dep"] == 0 and x["v_dep"] == 0.0 for x in t)
     assert sim.read()["x"].shape == (0, 3)
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_step_converts_the_pair_sums_like_the_evaluation(use_graph):
+    """In the step, k_finish turns the symmetric pair kernel's fixed-point sums into FP32 and clears the
+    accumulators; outside it (a force evaluation) k_pair_finish does.  After 7 steps (graph replay or
+    direct launches; 6,000 particles of the 65k recipe, every force on), the stored acceleration equals
+    bitwise that of a fresh evaluation at the same positions, twice in a row (the accumulators were
+    left at zero by both)."""
+    w = make_workload("single-65k", n=6000, field_n=32)
+    f = w.field()
+    sim, _ = seeded_pair(w.params, f, w.x, w.d, w.qbase, w.offsets, w.sample_params, 4, oracle=False)
+    sim.set_kernel_config(4, 2, 64, 2, use_graph=use_graph)
+    say("case: pair-sum conversion in the step, graph", use_graph)
+    sim.step(7)
+    a_step = sim.read()["a"]
+    for _ in range(2):
+        sim.eval_accel()
+        assert np.array_equal(sim.read()["a"], a_step)
