@@ -740,20 +740,22 @@ def test_fp32_symmetric_every_particle_of_uneven_samples(cfg):
         assert np.all(np.abs(F.sum(0)) <= 1e-6 * scale[sl].sum()), s
 
 
+@pytest.mark.parametrize("reorder", [0, 2])
 @pytest.mark.parametrize("real_bytes", [4, 8])
-def test_empty_single_and_pair_samples(real_bytes):
+def test_empty_single_and_pair_samples(real_bytes, reorder):
     """Samples of 0, 1, 2, 0, 65 and 300 particles in one layout (the default pair mode of the
     precision): every particle's acceleration at seed against the oracle, positions after 5 steps
     (FP64: round-off; FP32: within 1e-5 R), and per-sample tallies that conserve particles (the empty
-    samples tally nothing and report V_dep = 0)."""
+    samples tally nothing and report V_dep = 0); with and without the storage reorder (every 2 steps)."""
     w = make_workload("batched-256", n_samples=6, n_lo=100, n_hi=400, field_n=16)
     f = w.field()
     sizes = [0, 1, 2, 0, 65, 300]
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     n = int(off[-1])
     x, d, q = w.x[:n], w.d[:n], w.qbase[:n]
-    say("case: empty / single / pair samples, sizes", sizes, "fp", 8 * real_bytes)
+    say("case: empty / single / pair samples, sizes", sizes, "fp", 8 * real_bytes, "reorder", reorder)
     sim, ora = seeded_pair(w.params, f, x, d, q, off, w.sample_params, real_bytes)
+    sim.set_reorder(reorder)
     g = sim.read()
     tg = np.arange(n)
     e = force_error(g["a"], ora.a, coulomb_scale(ora, tg))
